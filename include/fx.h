@@ -1,0 +1,176 @@
+/*
+ * fx.h -- C ABI of the MI355X exchange-matrix library (libfx.so).
+ *
+ * The library builds the Fock exchange matrix of Challacombe & Bock, "An
+ * N-Body Solution to the Problem of Fock Exchange", Eq. (6), by the naive
+ * hextree traversal of Eqs. (7a-d) with the blocked Almlof-Ahlrichs metric
+ * query of Eq. (8), on one AMD Instinct MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ *  - Basis: contracted Cartesian Gaussian shells, l = 0 (s), 1 (p), 2 (d).
+ *    Functions are numbered shell after shell in the caller's shell order;
+ *    the components of a shell follow lexicographic Cartesian order
+ *    (p: x, y, z; d: xx, xy, xz, yy, yz, zz).  Every component is
+ *    normalised to (phi|phi) = 1.
+ *  - K convention (library scale, no -1/2):
+ *        K_{mu sig} = sum_{nu, lam} (mu nu|lam sig) P_{nu lam}
+ *    summed over the shell quartets (a,b,c,d) that survive the metric query
+ *        beta = (||Q_ab||_F * ||Q_cd||_F) * ||P_bc||_F  >  tau,
+ *    Q_{mu nu} = (mu nu|mu nu)^{1/2}, ||P_bc||_F the larger of the Frobenius
+ *    norms of the (b,c) and (c,b) blocks of P.  The paper's exchange matrix
+ *    (factor -1/2, Eq. 6) is obtained with alpha = -0.5 in fx_exchange_ex.
+ *    Because block Frobenius norms bound the norms of their sub-blocks (Eq.
+ *    8 and the sub-multiplicativity argument after it), the traversal culls
+ *    only work whose bound is <= tau, and the computed quartet set is exactly
+ *    {q : beta_q > tau}, independent of the tree.
+ *  - Matrices P and K are n x n, row-major, FP64, DEVICE memory owned by the
+ *    caller, indexed in the caller's function order.
+ *  - Every call returns fx_status; arguments are validated before any work
+ *    is enqueued; no C++ exception crosses this boundary.  On failure
+ *    fx_last_error_message() describes the cause (thread-local).
+ *  - hipStream_t is passed as void* so that this header needs no HIP header.
+ */
+#ifndef FX_H
+#define FX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fx_status {
+    FX_OK = 0,
+    FX_ERR_INVALID_ARG = 1,  /* null pointer, bad size, tau < 0 or NaN, ... */
+    FX_ERR_UNSUPPORTED = 2,  /* l > 2, more than FX_MAX_PRIM primitives     */
+    FX_ERR_OOM = 3,          /* device allocation failed                     */
+    FX_ERR_HIP = 4,          /* a HIP runtime call failed                    */
+    FX_ERR_INTERNAL = 5
+} fx_status;
+
+#define FX_MAX_L 2
+#define FX_MAX_PRIM 16
+
+/* Shells, HOST memory, read only during fx_build_quadtree.
+ *   l[nshell]        angular momentum 0..2
+ *   nprim[nshell]    primitives per shell, 1..FX_MAX_PRIM
+ *   center[3*nshell] shell centres in bohr
+ *   exps[sum nprim]  primitive exponents (bohr^-2), shell after shell
+ *   coefs[sum nprim] weights multiplying NORMALISED primitives; the library
+ *                    renormalises each contracted function.                */
+typedef struct fx_shells {
+    int32_t nshell;
+    const int32_t* l;
+    const int32_t* nprim;
+    const double* center;
+    const double* exps;
+    const double* coefs;
+} fx_shells;
+
+/* Tree options (NULL = defaults).
+ *   leaf_max_functions: the ragged bisection of Eq. (1) stops at blocks of
+ *     at most this many functions (or a single shell); default 10, as in the
+ *     paper's implementation (Section V: blocks of 10x10 or smaller).
+ *   ordering: 0 = Hilbert curve on shell centres (Section III, default),
+ *             1 = caller order. */
+typedef struct fx_tree_opts {
+    int32_t leaf_max_functions;
+    int32_t ordering;
+} fx_tree_opts;
+
+typedef struct fx_tree fx_tree;   /* opaque, immutable after build */
+
+/* Precision of the shell-quartet recursion.
+ *   FX_PREC_FP64:  every quartet in FP64.
+ *   FX_PREC_MIXED: quartets with beta < fp32_threshold run their VRR/HRR in
+ *                  FP32; Boys function, bounds, pair geometry and all
+ *                  accumulation into K stay FP64. */
+typedef enum fx_precision { FX_PREC_FP64 = 0, FX_PREC_MIXED = 1 } fx_precision;
+
+/* Work scheduling (never changes which quartets are computed, nor K: the
+ * per-block reduction is deterministic).
+ *   FX_SCHED_BOUND: units ordered by a cost estimate from bounds and counts.
+ *   FX_SCHED_MLP:   units ordered by the learned cost model given in
+ *                   fx_exchange_opts.costmodel (falls back to BOUND if NULL).
+ *   FX_SCHED_NONE:  traversal order. */
+typedef enum fx_schedule { FX_SCHED_BOUND = 0, FX_SCHED_MLP = 1, FX_SCHED_NONE = 2 } fx_schedule;
+
+typedef struct fx_costmodel fx_costmodel;
+
+typedef struct fx_exchange_opts {
+    int32_t precision;          /* fx_precision, default FX_PREC_FP64        */
+    double fp32_threshold;      /* default 1e-5                              */
+    int32_t schedule;           /* fx_schedule, default FX_SCHED_BOUND       */
+    const fx_costmodel* costmodel;
+    double alpha, beta;         /* K <- alpha*K_x + beta*K; default 1, 0     */
+    int64_t max_frontier_entries; /* traversal chunking threshold, 0 = auto  */
+} fx_exchange_opts;
+
+/* Statistics of one fx_exchange_ex call (valid when the call returns). */
+#define FX_STATS_MAX_LEVELS 32
+typedef struct fx_stats {
+    int32_t levels;                              /* tree depth + 1            */
+    int64_t frontier[FX_STATS_MAX_LEVELS];       /* surviving tasks per level */
+    int64_t leaf_items;                          /* surviving leaf (A,D) pairs */
+    int64_t units;                               /* K-block work units        */
+    int64_t quartets;                            /* computed shell quartets   */
+    int64_t quartets_fp32;                       /* of which in FP32          */
+    int64_t class_quartets[81];                  /* per (la lb|lc ld), ((la*3+lb)*3+lc)*3+ld */
+    double prim_quartets;                        /* primitive quartets        */
+    double flops;                                /* algorithmic flops (generated-code count) */
+    int32_t chunks;                              /* traversal chunks          */
+    double seconds_traversal, seconds_eri, seconds_total; /* host wall clock */
+} fx_stats;
+
+/* Build the basis-function tree for a set of shells: normalisation, shell
+ * ordering along a Hilbert curve (Section III), ragged bisection at shell
+ * boundaries (Eq. 1), shell-pair Schwarz factors Q and their Frobenius norms
+ * at every level of the pair quadtree (Eq. 2).  The handle owns its device
+ * memory.  Blocking: returns after the tree is built on `stream`. */
+fx_status fx_build_quadtree(const fx_shells* shells, const fx_tree_opts* opts, void* stream,
+                            fx_tree** out);
+
+/* K <- K_x(P) with the defaults of fx_exchange_ex (FP64, alpha 1, beta 0).
+ * P, K: device, n x n row-major FP64 (n = fx_nbf(tree)), caller order.
+ * tau >= 0 (tau = 0 culls only exactly-zero bounds).  K is overwritten; P
+ * must not alias K.  Work is ordered on `stream`; the call returns when K
+ * is complete (the traversal reads frontier sizes back to the host). */
+fx_status fx_exchange(const fx_tree* tree, const double* P, double tau, double* K, void* stream);
+
+/* As fx_exchange with options and statistics (stats may be NULL). */
+fx_status fx_exchange_ex(const fx_tree* tree, const double* P, double tau, double* K,
+                         const fx_exchange_opts* opts, fx_stats* stats, void* stream);
+
+/* Many independent systems in one call: trees[i], P[i], K[i] (host arrays of
+ * device pointers), all with the same tau and options.  The work of all
+ * systems shares one traversal per level and one launch per class. */
+fx_status fx_exchange_batched(const fx_tree* const* trees, const double* const* P, double* const* K,
+                              int32_t count, double tau, const fx_exchange_opts* opts,
+                              fx_stats* stats, void* stream);
+
+/* Number of basis functions. */
+int32_t fx_nbf(const fx_tree* tree);
+/* Number of shells. */
+int32_t fx_nshell(const fx_tree* tree);
+/* perm[i] = caller index of the i-th shell in the tree's (Hilbert) order; host array of nshell. */
+fx_status fx_tree_perm(const fx_tree* tree, int32_t* perm);
+/* Depth of the tree (number of levels) and nodes per level (host array, may be NULL). */
+int32_t fx_tree_levels(const fx_tree* tree, int64_t* nodes_per_level);
+/* Copy the shell-pair Schwarz norms ||Q_ab||_F (caller shell order, nshell^2, host). */
+fx_status fx_tree_schwarz(const fx_tree* tree, double* Qn_host);
+void fx_tree_free(fx_tree* tree);
+
+/* Device allocator used for all library memory (NULL, NULL restores
+ * hipMallocAsync / hipFreeAsync).  Not thread-safe against running calls. */
+typedef void* (*fx_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*fx_free_fn)(void* ptr, void* stream, void* ctx);
+fx_status fx_set_allocator(fx_alloc_fn alloc, fx_free_fn free_, void* ctx);
+
+const char* fx_status_string(fx_status s);
+const char* fx_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FX_H */

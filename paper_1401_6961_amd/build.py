@@ -1,0 +1,90 @@
+"""Build libfx.so for gfx950: generate the class kernels, compile every HIP
+and C++ source with hipcc (in parallel), link the shared library in-tree.
+
+build(incremental=False) recompiles everything; with incremental=True (or
+FX_BUILD_INCREMENTAL=1) objects whose source, headers and flags are
+unchanged are reused from _build/.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import hashlib
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+GEN = os.path.join(CSRC, "gen")
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(PKG, "libfx.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-I", CSRC, "-I", GEN, "-I", os.path.join(ROOT, "include"),
+             "-Wno-unused-variable", "-Wno-unused-lambda-capture"]
+
+
+def _sources():
+    srcs = [os.path.join(CSRC, f) for f in ("fx_kernels.hip", "fx_host.cpp", "fx_costmodel.hip")
+            if os.path.exists(os.path.join(CSRC, f))]
+    srcs += sorted(os.path.join(GEN, f) for f in os.listdir(GEN) if f.endswith(".hip"))
+    return srcs
+
+
+def _headers_digest():
+    h = hashlib.sha256()
+    for d in (CSRC, GEN, os.path.join(ROOT, "include")):
+        for f in sorted(os.listdir(d)):
+            if f.endswith(".h"):
+                h.update(f.encode())
+                h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def _compile(src, hdr_digest, incremental):
+    h = hashlib.sha256()
+    h.update(open(src, "rb").read())
+    h.update(hdr_digest.encode())
+    h.update(" ".join(HIP_FLAGS).encode())
+    obj = os.path.join(BUILD, os.path.basename(src) + "." + h.hexdigest()[:16] + ".o")
+    if incremental and os.path.exists(obj):
+        return obj
+    tmp = obj + ".tmp"
+    cmd = [HIPCC] + HIP_FLAGS + ["-x", "hip", "-c", src, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {src}\n{r.stderr[-4000:]}")
+    os.replace(tmp, obj)
+    return obj
+
+
+def build(incremental: bool | None = None, jobs: int | None = None) -> str:
+    if incremental is None:
+        incremental = os.environ.get("FX_BUILD_INCREMENTAL", "0") == "1"
+    os.makedirs(BUILD, exist_ok=True)
+    sys.path.insert(0, CSRC)
+    import gen_eri  # noqa: E402
+    gen_eri.main(GEN)
+    digest = _headers_digest()
+    srcs = _sources()
+    # biggest sources first so the long compiles start early
+    srcs.sort(key=lambda s: -os.path.getsize(s))
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, digest, incremental), srcs))
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed\n{r.stderr[-4000:]}")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    inc = "--incremental" in sys.argv
+    print(build(incremental=inc))

@@ -1,0 +1,260 @@
+// Device-side building blocks shared by the generated shell-quartet class
+// kernels: the Boys function, shell references, and the work-unit loop that
+// screens, compacts and evaluates the quartets of one exchange K block.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fx_internal.h"
+
+#define FX_TWO_PI_POW_2_5 34.98683665524972497   // 2 pi^{5/2}
+
+struct FxShellRef {
+    double x, y, z;
+    int nprim, pofs;
+};
+
+__device__ __forceinline__ FxShellRef fx_shell(const FxDevBasis& B, int s) {
+    FxShellRef r;
+    r.x = B.xyz[3 * s];
+    r.y = B.xyz[3 * s + 1];
+    r.z = B.xyz[3 * s + 2];
+    r.nprim = B.nprim[s];
+    r.pofs = B.pofs[s];
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Boys function F_m(T), m = 0..M, FP64.
+//   T < FX_BOYS_TMAX: 6th-order Taylor expansion of F_M about the nearest
+//   tabulated point T_i = i/32 (dF_m/dT = -F_{m+1}), then the downward
+//   recursion F_m = (2T F_{m+1} + e^{-T}) / (2m+1).
+//   T >= FX_BOYS_TMAX: F_0 = (1/2) sqrt(pi/T) (erf(sqrt T) = 1 to FP64) and
+//   the upward recursion F_{m+1} = ((2m+1) F_m - e^{-T}) / (2T), stable for
+//   T > m + 1/2.
+// The table (F_j(T_i), j = 0..FX_BOYS_NCOL-1) is built on the host.
+// ---------------------------------------------------------------------------
+template <int M>
+__device__ __forceinline__ void fx_boys(double T, const double* __restrict__ tab, double* F) {
+    if (T < FX_BOYS_TMAX) {
+        const int i = (int)(T * FX_BOYS_INV_DT + 0.5);
+        const double dt = (double)i * FX_BOYS_DT - T;   // T_i - T
+        const double* r = tab + i * FX_BOYS_NCOL + M;
+        double f = r[6] * (dt * (1.0 / 6.0));
+        f = (r[5] + f) * (dt * (1.0 / 5.0));
+        f = (r[4] + f) * (dt * (1.0 / 4.0));
+        f = (r[3] + f) * (dt * (1.0 / 3.0));
+        f = (r[2] + f) * (dt * 0.5);
+        f = (r[1] + f) * dt;
+        F[M] = r[0] + f;
+        if (M > 0) {
+            const double eT = exp(-T), T2 = 2.0 * T;
+#pragma unroll
+            for (int m = M - 1; m >= 0; --m) F[m] = (T2 * F[m + 1] + eT) * (1.0 / (2 * m + 1));
+        }
+    } else {
+        const double oT = 1.0 / T;
+        F[0] = 0.88622692545275801365 * sqrt(oT);   // sqrt(pi)/2 / sqrt(T)
+        if (M > 0) {
+            const double eT = exp(-T), h = 0.5 * oT;
+#pragma unroll
+            for (int m = 0; m < M; ++m) F[m + 1] = ((2 * m + 1) * F[m] - eT) * h;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// wave-level helpers (wave64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int fx_lane() { return (int)(threadIdx.x & 63); }
+
+__device__ __forceinline__ void fx_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int fx_wave_max(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        int o = __shfl_xor(v, off, 64);
+        v = v > o ? v : o;
+    }
+    return v;
+}
+
+// all-reduce sum; every lane obtains bitwise the same value (each butterfly
+// step adds the same two operands on both partner lanes)
+__device__ __forceinline__ double fx_wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int fx_mbcnt(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+constexpr int fx_ncart(int l) { return (l + 1) * (l + 2) / 2; }
+
+// Per-component normalisation factors sqrt((2l-1)!!/((2i-1)!!(2j-1)!!(2k-1)!!)),
+// lexicographic Cartesian order; only d has factors other than 1.
+__device__ __forceinline__ double fx_comp_factor(int l, int k) {
+    if (l < 2) return 1.0;
+    return (k == 1 || k == 2 || k == 4) ? 1.7320508075688772935 : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// Work-unit loop of one class kernel.
+//
+// A unit is a K block (a, d) inside a surviving leaf item (A, D) of the
+// hextree traversal; its candidate quartets are (a, b, c, d) with (B, C) in
+// the item's surviving list, b in B and c in C of the class's angular
+// momenta.  The shell-level metric query of Eq. (8) decides each candidate;
+// survivors are compacted by wave ballot into an LDS queue in a fixed order
+// and evaluated 64 at a time, one per lane.  Each lane accumulates its
+// quartets' contributions to K_ad in FP64 registers; the 64 partial blocks
+// are reduced by a fixed butterfly, so the block is a deterministic function
+// of the unit, whatever order units are scheduled in.  The block is written
+// once to this class's (lb, lc, precision) slot: no atomics.
+// ---------------------------------------------------------------------------
+template <int LA, int LB, int LC, int LD, typename Fn>
+__device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
+    constexpr int NA = fx_ncart(LA), ND = fx_ncart(LD);
+    __shared__ int2 queue[FX_CLASS_WAVES][128];
+    const int lane = fx_lane();
+    const int wave = (int)(threadIdx.x >> 6);
+    const long slot_unit = (long)blockIdx.x * FX_CLASS_WAVES + wave;
+    if (slot_unit >= A.nunits) return;
+    const int u = A.order ? A.order[slot_unit] : (int)slot_unit;
+    const int item = A.units[3 * u], a = A.units[3 * u + 1], d = A.units[3 * u + 2];
+    const FxDevBasis& Bs = A.basis;
+    const int S = Bs.nshell;
+    const FxShellRef ra = fx_shell(Bs, a), rd = fx_shell(Bs, d);
+    const double* __restrict__ Qa = Bs.Qn + (long)a * S;
+    const double* __restrict__ Qd = Bs.Qn + (long)d * S;
+    const double tau = A.tau, thr = A.thr;
+    const int mode = A.mode;
+    double kacc[NA * ND];
+#pragma unroll
+    for (int i = 0; i < NA * ND; ++i) kacc[i] = 0.0;
+
+    const long e0 = A.bc_off[item], e1 = A.bc_off[item + 1];
+    int qn = 0;
+    long nq = 0, npq = 0;
+    auto evaluate = [&](int2 q) {
+        const FxShellRef rb = fx_shell(Bs, q.x), rc = fx_shell(Bs, q.y);
+        npq += (long)(ra.nprim * rb.nprim) * (rc.nprim * rd.nprim);
+        const double* Pblk = A.P + (long)Bs.f0[q.x] * A.n + Bs.f0[q.y];
+        fn(ra, rb, rc, rd, Bs.exps, Bs.coefs, A.boys, Pblk, A.n, kacc);
+    };
+    for (long base = e0; base < e1; base += 64) {
+        const long e = base + lane;
+        int nb = 0, nc = 0, ob = 0, oc = 0;
+        if (e < e1) {
+            const int2 bc = A.bc[e];
+            ob = Bs.leaf_lofs[bc.x * 4 + LB];
+            nb = Bs.leaf_lofs[bc.x * 4 + LB + 1] - ob;
+            oc = Bs.leaf_lofs[bc.y * 4 + LC];
+            nc = Bs.leaf_lofs[bc.y * 4 + LC + 1] - oc;
+        }
+        const int ncand = nb * nc;
+        const int maxc = fx_wave_max(ncand);
+        for (int k = 0; k < maxc; ++k) {
+            bool ok = false;
+            int b = 0, c = 0;
+            if (k < ncand) {
+                const int kb = k / nc;
+                b = Bs.leaf_lsh[ob + kb];
+                c = Bs.leaf_lsh[oc + (k - kb * nc)];
+                const double beta = (Qa[b] * Qd[c]) * A.Pn[(long)b * S + c];
+                ok = beta > tau;
+                if (mode == FX_MODE_MIXED_HI) ok = ok && !(beta < thr);
+                else if (mode == FX_MODE_MIXED_LO) ok = ok && (beta < thr);
+            }
+            const uint64_t m = __ballot(ok);
+            if (ok) queue[wave][qn + fx_mbcnt(m)] = make_int2(b, c);
+            qn += __popcll(m);
+            fx_wave_sync();
+            if (qn >= 64) {
+                const int2 q = queue[wave][lane];
+                const int2 t = queue[wave][lane + 64];
+                evaluate(q);
+                nq += 64;
+                fx_wave_sync();
+                queue[wave][lane] = t;
+                qn -= 64;
+                fx_wave_sync();
+            }
+        }
+    }
+    if (qn > 0) {
+        if (lane < qn) evaluate(queue[wave][lane]);
+        nq += qn;
+    }
+    // deterministic reduction of the 64 lane partials, then one write per element
+    const long rowbase = (long)Bs.f0[a] * A.n + Bs.f0[d];
+    double outv = 0.0;
+#pragma unroll
+    for (int i = 0; i < NA * ND; ++i) {
+        const double s = fx_wave_sum(kacc[i]);
+        if (lane == i) outv = s * (fx_comp_factor(LA, i / ND) * fx_comp_factor(LD, i % ND));
+    }
+    if (lane < NA * ND) A.kslot[rowbase + (long)(lane / ND) * A.n + (lane % ND)] = outv;
+    if (A.counters) {
+        long np = npq;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) np += __shfl_xor(np, off, 64);
+        if (lane == 0) {
+            atomicAdd(A.counters, (unsigned long long)nq);
+            atomicAdd(A.counters + 1, (unsigned long long)np);
+        }
+    }
+}
+
+#define FX_DEFINE_CLASS_KERNELS(la, lb, lc, ld, cls)                                                   \
+    __global__ __launch_bounds__(64 * FX_CLASS_WAVES) void fx_k_##cls##_f64(FxClassArgs A) {            \
+        fx_class_body<la, lb, lc, ld>(A, [](const FxShellRef& ra, const FxShellRef& rb,                 \
+                                            const FxShellRef& rc, const FxShellRef& rd, const double* e,  \
+                                            const double* c, const double* bt, const double* P, long n,   \
+                                            double* k) { eri_##cls##_f64(ra, rb, rc, rd, e, c, bt, P, n, k); }); \
+    }                                                                                                   \
+    __global__ __launch_bounds__(64 * FX_CLASS_WAVES) void fx_k_##cls##_f32(FxClassArgs A) {            \
+        fx_class_body<la, lb, lc, ld>(A, [](const FxShellRef& ra, const FxShellRef& rb,                 \
+                                            const FxShellRef& rc, const FxShellRef& rd, const double* e,  \
+                                            const double* c, const double* bt, const double* P, long n,   \
+                                            double* k) { eri_##cls##_f32(ra, rb, rc, rd, e, c, bt, P, n, k); }); \
+    }                                                                                                   \
+    void fx_launch_##cls(int prec32, FxClassArgs A, int grid, hipStream_t st) {                         \
+        if (prec32) hipLaunchKernelGGL(fx_k_##cls##_f32, dim3(grid), dim3(64 * FX_CLASS_WAVES), 0, st, A); \
+        else hipLaunchKernelGGL(fx_k_##cls##_f64, dim3(grid), dim3(64 * FX_CLASS_WAVES), 0, st, A);     \
+    }
+
+// Schwarz factors: one thread per unordered shell pair (a <= b) of the pair
+// type (la, lb); Qn[a][b] = Qn[b][a] = sqrt(sum max(0, (mu nu|mu nu))).
+#define FX_SCHWARZ_CASE(la, lb, cls)                                                                    \
+    case (la * 3 + lb): s2 = eri_diag_##cls##_f64(r0, r1, B.exps, B.coefs, boys); break;
+
+#define FX_DEFINE_SCHWARZ_KERNEL()                                                                      \
+    __global__ __launch_bounds__(256) void fx_k_schwarz(FxDevBasis B, const double* boys, const int2* pairs, \
+                                                        long npairs, double* Qn) {                       \
+        const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;                                     \
+        if (i >= npairs) return;                                                                         \
+        const int a = pairs[i].x, b = pairs[i].y;                                                        \
+        const FxShellRef r0 = fx_shell(B, a), r1 = fx_shell(B, b);                                       \
+        double s2 = 0.0;                                                                                 \
+        switch (B.l[a] * 3 + B.l[b]) {                                                                   \
+            FX_SCHWARZ_CASE(0, 0, ssss) FX_SCHWARZ_CASE(0, 1, spsp) FX_SCHWARZ_CASE(0, 2, sdsd)          \
+            FX_SCHWARZ_CASE(1, 0, psps) FX_SCHWARZ_CASE(1, 1, pppp) FX_SCHWARZ_CASE(1, 2, pdpd)          \
+            FX_SCHWARZ_CASE(2, 0, dsds) FX_SCHWARZ_CASE(2, 1, dpdp) FX_SCHWARZ_CASE(2, 2, dddd)          \
+        }                                                                                                \
+        const double v = sqrt(s2);                                                                       \
+        Qn[(long)a * B.nshell + b] = v;                                                                  \
+        Qn[(long)b * B.nshell + a] = v;                                                                  \
+    }                                                                                                    \
+    void fx_launch_schwarz(FxDevBasis B, const double* boys, const int2* pairs, long npairs, double* Qn, \
+                           hipStream_t st) {                                                             \
+        if (npairs > 0)                                                                                  \
+            hipLaunchKernelGGL(fx_k_schwarz, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, B, \
+                               boys, pairs, npairs, Qn);                                                 \
+    }

@@ -1,0 +1,870 @@
+// Host planner and C ABI of the exchange library.
+//
+//  * tree build: normalisation of contracted shells, shell ordering along a
+//    3D Hilbert curve (Section III), ragged bisection at shell boundaries
+//    (Eq. 1), Schwarz factors of every shell pair and squared Frobenius
+//    norms of the shell-pair quadtree at every level (Eq. 2, Eq. 8);
+//  * exchange: density norms, the level-synchronous hextree traversal of
+//    Eqs. (7a-d) with the metric query of Eq. (8) (chunked when a level
+//    would exceed the frontier budget), K-block work units, one launch per
+//    angular-momentum class and precision, deterministic final reduction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/fx.h"
+#include "eri_flops.h"
+#include "eri_table.h"
+#include "fx_costmodel.h"
+#include "fx_internal.h"
+#include "fx_kernels.h"
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+struct FxError {
+    fx_status st;
+    std::string msg;
+};
+
+[[noreturn]] static void fx_fail(fx_status st, const std::string& msg) { throw FxError{st, msg}; }
+
+#define FX_HIP(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess) fx_fail(FX_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static fx_status fx_guard_status(const FxError& e) {
+    g_last_error = e.msg;
+    return e.st;
+}
+
+template <typename F>
+static fx_status fx_guard(F&& f) {
+    try {
+        f();
+        g_last_error.clear();
+        return FX_OK;
+    } catch (const FxError& e) {
+        return fx_guard_status(e);
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return FX_ERR_OOM;
+    } catch (...) {
+        g_last_error = "internal error";
+        return FX_ERR_INTERNAL;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------
+static fx_alloc_fn g_alloc = nullptr;
+static fx_free_fn g_free = nullptr;
+static void* g_alloc_ctx = nullptr;
+
+static void* fx_dalloc(size_t bytes, hipStream_t st, bool persistent = false) {
+    if (bytes == 0) bytes = 8;
+    void* p = nullptr;
+    if (persistent) {
+        // memory owned by a tree handle outlives the caller's stream
+        if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            fx_fail(FX_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        }
+        return p;
+    }
+    if (g_alloc) {
+        p = g_alloc(bytes, (void*)st, g_alloc_ctx);
+        if (!p) fx_fail(FX_ERR_OOM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes");
+        return p;
+    }
+    hipError_t e = hipMallocAsync(&p, bytes, st);
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        fx_fail(FX_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    return p;
+}
+
+static void fx_dfree(void* p, hipStream_t st, bool persistent = false) {
+    if (!p) return;
+    if (persistent) {
+        (void)hipFree(p);
+        return;
+    }
+    if (g_free) g_free(p, (void*)st, g_alloc_ctx);
+    else (void)hipFreeAsync(p, st);
+}
+
+// RAII set of device allocations tied to a stream
+struct DevArena {
+    hipStream_t st;
+    bool persistent;
+    std::vector<void*> ptrs;
+    explicit DevArena(hipStream_t s, bool pers = false) : st(s), persistent(pers) {}
+    template <typename T>
+    T* get(size_t count) {
+        T* p = (T*)fx_dalloc(sizeof(T) * count, st, persistent);
+        ptrs.push_back(p);
+        return p;
+    }
+    void release(void* p) {
+        auto it = std::find(ptrs.begin(), ptrs.end(), p);
+        if (it != ptrs.end()) {
+            fx_dfree(p, st, persistent);
+            ptrs.erase(it);
+        }
+    }
+    ~DevArena() {
+        for (void* p : ptrs) fx_dfree(p, st, persistent);
+    }
+};
+
+template <typename T>
+static T* upload(DevArena& A, const std::vector<T>& v) {
+    T* d = A.get<T>(v.size());
+    if (!v.empty()) FX_HIP(hipMemcpyAsync(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, A.st));
+    return d;
+}
+
+template <typename T>
+static T read1(const T* dptr, hipStream_t st) {
+    T v;
+    FX_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, st));
+    FX_HIP(hipStreamSynchronize(st));
+    return v;
+}
+
+static int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+
+// ---------------------------------------------------------------------------
+// Boys table F_j(T_i), T_i = i/32: the convergent series
+// F_j(T) = e^{-T} sum_k (2T)^k / ((2j+1)(2j+3)...(2j+2k+1)) in long double.
+// ---------------------------------------------------------------------------
+static std::vector<double> boys_table() {
+    std::vector<double> tab((size_t)FX_BOYS_NROW * FX_BOYS_NCOL);
+    for (int i = 0; i < FX_BOYS_NROW; ++i) {
+        const long double T = (long double)i * (long double)FX_BOYS_DT;
+        const long double eT = expl(-T);
+        for (int j = 0; j < FX_BOYS_NCOL; ++j) {
+            long double term = 1.0L / (2 * j + 1), sum = term;
+            for (int k = 1; k < 4000; ++k) {
+                term *= 2.0L * T / (long double)(2 * j + 2 * k + 1);
+                sum += term;
+                if (term < 1e-22L * sum) break;
+            }
+            tab[(size_t)i * FX_BOYS_NCOL + j] = (double)(eT * sum);
+        }
+    }
+    return tab;
+}
+
+// ---------------------------------------------------------------------------
+// 3D Hilbert curve: index of an integer point on a 2^bits grid (Skilling's
+// transposed-axes construction: undo excess work, Gray-encode, then
+// interleave the bits most significant first).
+// ---------------------------------------------------------------------------
+extern "C" uint64_t fx_hilbert_key3(uint32_t x, uint32_t y, uint32_t z, int32_t bits) {
+    uint32_t X[3] = {x, y, z};
+    const uint32_t top = 1u << (bits - 1);
+    for (uint32_t q = top; q > 1; q >>= 1) {
+        const uint32_t p = q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & q) {
+                X[0] ^= p;
+            } else {
+                const uint32_t t = (X[0] ^ X[i]) & p;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint32_t t = 0;
+    for (uint32_t q = top; q > 1; q >>= 1)
+        if (X[2] & q) t ^= q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= t;
+    uint64_t key = 0;
+    for (int b = bits - 1; b >= 0; --b)
+        for (int i = 0; i < 3; ++i) key = (key << 1) | ((X[i] >> b) & 1u);
+    return key;
+}
+
+// ---------------------------------------------------------------------------
+// host plan: ordering + ragged bisection
+// ---------------------------------------------------------------------------
+struct Level {
+    std::vector<int> sL, sR, ch0, nch;  // nodes of this level; ch0/nch index level+1
+};
+
+struct Plan {
+    std::vector<int> order;   // tree position -> caller shell index
+    std::vector<Level> levels;
+};
+
+static void validate_shells(const fx_shells* s) {
+    if (!s) fx_fail(FX_ERR_INVALID_ARG, "shells is NULL");
+    if (s->nshell <= 0) fx_fail(FX_ERR_INVALID_ARG, "nshell must be positive");
+    if (!s->l || !s->nprim || !s->center || !s->exps || !s->coefs)
+        fx_fail(FX_ERR_INVALID_ARG, "a shell array pointer is NULL");
+    long nf = 0, npt = 0;
+    for (int i = 0; i < s->nshell; ++i) {
+        if (s->l[i] < 0 || s->l[i] > FX_MAX_L) fx_fail(FX_ERR_UNSUPPORTED, "shell " + std::to_string(i) + ": l outside 0..2");
+        if (s->nprim[i] < 1 || s->nprim[i] > FX_MAX_PRIM)
+            fx_fail(FX_ERR_UNSUPPORTED, "shell " + std::to_string(i) + ": primitive count outside 1..16");
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(s->center[3 * i + k])) fx_fail(FX_ERR_INVALID_ARG, "non-finite shell centre");
+        nf += ncart(s->l[i]);
+        npt += s->nprim[i];
+    }
+    for (long p = 0; p < npt; ++p)
+        if (!(s->exps[p] > 0.0) || !std::isfinite(s->exps[p]) || !std::isfinite(s->coefs[p]))
+            fx_fail(FX_ERR_INVALID_ARG, "exponents must be positive and weights finite");
+    if (nf > (1L << 30)) fx_fail(FX_ERR_UNSUPPORTED, "too many basis functions");
+}
+
+static Plan make_plan(const fx_shells* s, const fx_tree_opts* opts) {
+    const int S = s->nshell;
+    const int leaf_max = (opts && opts->leaf_max_functions > 0) ? opts->leaf_max_functions : 10;
+    const int ordering = opts ? opts->ordering : 0;
+    if (opts && (opts->ordering < 0 || opts->ordering > 1)) fx_fail(FX_ERR_INVALID_ARG, "ordering must be 0 or 1");
+    Plan P;
+    P.order.resize(S);
+    std::iota(P.order.begin(), P.order.end(), 0);
+    if (ordering == 0 && S > 1) {
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int i = 0; i < S; ++i)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = std::min(lo[k], s->center[3 * i + k]);
+                hi[k] = std::max(hi[k], s->center[3 * i + k]);
+            }
+        double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-30});
+        const int bits = 21;
+        const double scale = (double)((1u << bits) - 1) / ext;
+        std::vector<uint64_t> key(S);
+        for (int i = 0; i < S; ++i) {
+            uint32_t q[3];
+            for (int k = 0; k < 3; ++k) q[k] = (uint32_t)std::llround((s->center[3 * i + k] - lo[k]) * scale);
+            key[i] = fx_hilbert_key3(q[0], q[1], q[2], bits);
+        }
+        std::stable_sort(P.order.begin(), P.order.end(), [&](int a, int b) { return key[a] < key[b]; });
+    }
+    // function prefix in tree order
+    std::vector<long> fp(S + 1, 0);
+    for (int i = 0; i < S; ++i) fp[i + 1] = fp[i] + ncart(s->l[P.order[i]]);
+    // breadth-first ragged bisection; leaves are carried to the deepest level
+    std::vector<std::pair<int, int>> cur{{0, S}};
+    while (true) {
+        Level L;
+        std::vector<std::pair<int, int>> next;
+        bool any_split = false;
+        for (auto [lo, hi] : cur) {
+            L.sL.push_back(lo);
+            L.sR.push_back(hi);
+            L.ch0.push_back((int)next.size());
+            const long nf = fp[hi] - fp[lo];
+            if (nf <= leaf_max || hi - lo == 1) {
+                next.push_back({lo, hi});
+                L.nch.push_back(1);
+            } else {
+                // split at the shell boundary closest to the function midpoint (ties: lower)
+                const double mid = 0.5 * (double)(fp[lo] + fp[hi]);
+                int best = lo + 1;
+                double bd = 1e300;
+                for (int m = lo + 1; m < hi; ++m) {
+                    const double d = std::fabs((double)fp[m] - mid);
+                    if (d < bd) {
+                        bd = d;
+                        best = m;
+                    }
+                }
+                next.push_back({lo, best});
+                next.push_back({best, hi});
+                L.nch.push_back(2);
+                any_split = true;
+            }
+        }
+        P.levels.push_back(std::move(L));
+        if (!any_split) break;
+        cur.swap(next);
+        if (P.levels.size() >= FX_STATS_MAX_LEVELS - 1) fx_fail(FX_ERR_INTERNAL, "tree too deep");
+    }
+    // the last level: every node is a leaf (nch = 1 pointing to itself, unused)
+    return P;
+}
+
+// ---------------------------------------------------------------------------
+// the tree handle
+// ---------------------------------------------------------------------------
+struct fx_tree {
+    int S = 0, n = 0, lmax = 0;
+    std::vector<int> order;          // tree position -> caller shell
+    std::vector<int> l, nprim;       // tree order
+    std::vector<int> f0;             // tree order, caller function offset
+    std::vector<Level> levels;
+    std::vector<int> leaf_lofs;      // host copy
+    hipStream_t build_stream = nullptr;
+    DevArena* arena = nullptr;
+    FxDevBasis basis{};
+    double* boys = nullptr;
+    std::vector<int*> d_sL, d_sR, d_ch0, d_nch;
+    std::vector<double*> d_Qsq;      // per level (nk x nk)
+    ~fx_tree() {
+        if (arena) (void)hipDeviceSynchronize();
+        delete arena;
+    }
+};
+
+static void build_tree(const fx_shells* s, const fx_tree_opts* opts, hipStream_t st, fx_tree* T) {
+    validate_shells(s);
+    Plan P = make_plan(s, opts);
+    const int S = s->nshell;
+    T->S = S;
+    T->order = P.order;
+    T->levels = P.levels;
+    // caller-order offsets
+    std::vector<long> cpofs(S + 1, 0), cf0(S + 1, 0);
+    for (int i = 0; i < S; ++i) {
+        cpofs[i + 1] = cpofs[i] + s->nprim[i];
+        cf0[i + 1] = cf0[i] + ncart(s->l[i]);
+    }
+    T->n = (int)cf0[S];
+    // tree-order shell data with normalised radial weights:
+    //   c_p = d_p N_p / sqrt(sum_pq d_p d_q N_p N_q (2l-1)!! / (2 g)^l (pi/g)^{3/2}),
+    //   N_p = (2a/pi)^{3/4} (4a)^{l/2} / sqrt((2l-1)!!)   (component x^l)
+    std::vector<int> l(S), np(S), pofs(S), f0(S);
+    std::vector<double> xyz(3 * S), ex, co;
+    for (int t = 0; t < S; ++t) {
+        const int i = P.order[t];
+        l[t] = s->l[i];
+        np[t] = s->nprim[i];
+        pofs[t] = (int)ex.size();
+        f0[t] = (int)cf0[i];
+        for (int k = 0; k < 3; ++k) xyz[3 * t + k] = s->center[3 * i + k];
+        const int L = l[t];
+        double df = 1.0;
+        for (int k = 2 * L - 1; k > 1; k -= 2) df *= k;
+        std::vector<double> N(np[t]);
+        for (int p = 0; p < np[t]; ++p) {
+            const double a = s->exps[cpofs[i] + p];
+            N[p] = std::pow(2.0 * a / M_PI, 0.75) * std::pow(4.0 * a, 0.5 * L) / std::sqrt(df);
+        }
+        double ovl = 0.0;
+        for (int p = 0; p < np[t]; ++p)
+            for (int q = 0; q < np[t]; ++q) {
+                const double g = s->exps[cpofs[i] + p] + s->exps[cpofs[i] + q];
+                ovl += s->coefs[cpofs[i] + p] * s->coefs[cpofs[i] + q] * N[p] * N[q] * df / std::pow(2.0 * g, L) *
+                       std::pow(M_PI / g, 1.5);
+            }
+        if (!(ovl > 0.0)) fx_fail(FX_ERR_INVALID_ARG, "shell " + std::to_string(i) + " has zero norm");
+        for (int p = 0; p < np[t]; ++p) {
+            ex.push_back(s->exps[cpofs[i] + p]);
+            co.push_back(s->coefs[cpofs[i] + p] * N[p] / std::sqrt(ovl));
+        }
+        T->lmax = std::max(T->lmax, L);
+    }
+    T->l = l;
+    T->nprim = np;
+    T->f0 = f0;
+    // leaf shell lists per l
+    const Level& leaf = P.levels.back();
+    const int nleaf = (int)leaf.sL.size();
+    std::vector<int> lofs(nleaf * 4), lsh;
+    for (int A = 0; A < nleaf; ++A) {
+        for (int L = 0; L < 3; ++L) {
+            lofs[A * 4 + L] = (int)lsh.size();
+            for (int t = leaf.sL[A]; t < leaf.sR[A]; ++t)
+                if (l[t] == L) lsh.push_back(t);
+        }
+        lofs[A * 4 + 3] = (int)lsh.size();
+    }
+    T->leaf_lofs = lofs;
+
+    T->arena = new DevArena(st, true);
+    DevArena& A = *T->arena;
+    FxDevBasis& B = T->basis;
+    B.nshell = S;
+    B.nbf = T->n;
+    B.l = upload(A, l);
+    B.nprim = upload(A, np);
+    B.pofs = upload(A, pofs);
+    B.f0 = upload(A, f0);
+    B.xyz = upload(A, xyz);
+    B.exps = upload(A, ex);
+    B.coefs = upload(A, co);
+    B.leaf_lofs = upload(A, lofs);
+    B.leaf_lsh = upload(A, lsh.empty() ? std::vector<int>{0} : lsh);
+    T->boys = upload(A, boys_table());
+    for (const Level& L : P.levels) {
+        T->d_sL.push_back(upload(A, L.sL));
+        T->d_sR.push_back(upload(A, L.sR));
+        T->d_ch0.push_back(upload(A, L.ch0));
+        T->d_nch.push_back(upload(A, L.nch));
+    }
+    // Schwarz norms of all shell pairs
+    double* Qn = A.get<double>((size_t)S * S);
+    B.Qn = Qn;
+    {
+        std::vector<int2> pairs;
+        pairs.reserve((size_t)S * (S + 1) / 2);
+        for (int a = 0; a < S; ++a)
+            for (int b = a; b < S; ++b) pairs.push_back(make_int2(a, b));
+        DevArena tmp(st);
+        int2* dp = upload(tmp, pairs);
+        fx_launch_schwarz(B, T->boys, dp, (long)pairs.size(), Qn, st);
+        FX_HIP(hipGetLastError());
+        FX_HIP(hipStreamSynchronize(st));
+    }
+    // squared block norms of Q at every level
+    const int nl = (int)P.levels.size();
+    T->d_Qsq.resize(nl);
+    for (int k = nl - 1; k >= 0; --k) {
+        const int nk = (int)P.levels[k].sL.size();
+        T->d_Qsq[k] = A.get<double>((size_t)nk * nk);
+        if (k == nl - 1)
+            fx_launch_leaf_sq(Qn, S, T->d_sL[k], T->d_sR[k], nk, T->d_Qsq[k], st);
+        else
+            fx_launch_level_up(T->d_Qsq[k + 1], (int)P.levels[k + 1].sL.size(), T->d_ch0[k], T->d_nch[k], nk,
+                               T->d_Qsq[k], st);
+    }
+    FX_HIP(hipGetLastError());
+    FX_HIP(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------------------
+// exchange
+// ---------------------------------------------------------------------------
+struct Frontier {
+    int2* ad;
+    long* bc_off;      // absolute offsets into bc for ad[0..nad]
+    int2* bc;
+    int* parent;
+    int nad;
+    long e_begin, e_count;
+    int p_base;
+};
+
+struct ExCtx {
+    const fx_tree* T;
+    const double* P;
+    double tau;
+    hipStream_t st;
+    int precision;
+    double thr;
+    int schedule;
+    const fx_costmodel* cm;
+    long cap;
+    std::vector<double*> Psq;
+    double* Pn;
+    double* slots;
+    int nslot;
+    unsigned long long* counters;   // [2][81][2]: quartets, primitive quartets per class and precision
+    fx_stats* stats;
+    long* scan_partial;
+    long scan_partial_cap;
+    long* scan_total;
+    double seconds_eri = 0;
+};
+
+static int slot_index(const ExCtx& c, int lb, int lc, int prec32) {
+    const int L = c.T->lmax + 1;
+    return (lb * L + lc) * (c.precision == FX_PREC_MIXED ? 2 : 1) + prec32;
+}
+
+static long* scan_partial(ExCtx& c, DevArena& A, long n) {
+    const long need = fx_scan_tiles(n);
+    if (need > c.scan_partial_cap) return A.get<long>(need);
+    return c.scan_partial;
+}
+
+static void leaf_work(ExCtx& c, const Frontier& f) {
+    const fx_tree* T = c.T;
+    hipStream_t st = c.st;
+    DevArena A(st);
+    const long nitems = f.nad;
+    if (nitems == 0) return;
+    if (c.stats) c.stats->leaf_items += nitems;
+    int* cnt = A.get<int>(9 * nitems);
+    long* upos = A.get<long>(9 * nitems + 1);
+    fx_launch_unit_count(f.ad, nitems, T->basis.leaf_lofs, cnt, st);
+    fx_scan_i32(cnt, 9 * nitems, upos, scan_partial(c, A, 9 * nitems), c.scan_total, st);
+    std::vector<long> bounds(10);
+    for (int k = 0; k < 9; ++k) FX_HIP(hipMemcpyAsync(&bounds[k], upos + (long)k * nitems, sizeof(long), hipMemcpyDeviceToHost, st));
+    FX_HIP(hipMemcpyAsync(&bounds[9], upos + 9 * nitems, sizeof(long), hipMemcpyDeviceToHost, st));
+    FX_HIP(hipStreamSynchronize(st));
+    const long nunits = bounds[9];
+    if (c.stats) c.stats->units += nunits;
+    int* units = A.get<int>(3 * std::max(1L, nunits));
+    fx_launch_unit_write(f.ad, nitems, 0, T->basis.leaf_lofs, T->basis.leaf_lsh, upos, units, st);
+    FX_HIP(hipGetLastError());
+
+    FxClassArgs args{};
+    args.basis = T->basis;
+    args.boys = T->boys;
+    args.P = c.P;
+    args.n = T->n;
+    args.Pn = c.Pn;
+    args.bc_off = f.bc_off;
+    args.bc = f.bc;
+    args.tau = c.tau;
+    args.thr = c.thr;
+    const int Lm = T->lmax;
+    for (int la = 0; la <= Lm; ++la)
+        for (int ld = 0; ld <= Lm; ++ld) {
+            const int cls2 = la * 3 + ld;
+            const long u0 = bounds[cls2], u1 = bounds[cls2 + 1];
+            if (u1 <= u0) continue;
+            args.units = units + 3 * u0;
+            args.nunits = u1 - u0;
+            args.order = nullptr;
+            const int grid = (int)((args.nunits + FX_CLASS_WAVES - 1) / FX_CLASS_WAVES);
+            for (int lb = 0; lb <= Lm; ++lb)
+                for (int lc = 0; lc <= Lm; ++lc) {
+                    const int cls = ((la * 3 + lb) * 3 + lc) * 3 + ld;
+                    const int nprec = c.precision == FX_PREC_MIXED ? 2 : 1;
+                    for (int pr = 0; pr < nprec; ++pr) {
+                        args.mode = c.precision == FX_PREC_MIXED ? (pr ? FX_MODE_MIXED_LO : FX_MODE_MIXED_HI)
+                                                                 : FX_MODE_ALL;
+                        args.kslot = c.slots + (long)slot_index(c, lb, lc, pr) * T->n * T->n;
+                        args.counters = c.counters + (cls * 2 + pr) * 2;
+                        fx_class_table[cls](pr, args, grid, st);
+                    }
+                }
+        }
+    FX_HIP(hipGetLastError());
+    FX_HIP(hipStreamSynchronize(st));
+}
+
+static void traverse(ExCtx& c, int k, const Frontier& f) {
+    const fx_tree* T = c.T;
+    hipStream_t st = c.st;
+    const int nl = (int)T->levels.size();
+    if (c.stats) c.stats->frontier[k] += f.e_count;
+    if (k == nl - 1) {
+        auto t0 = std::chrono::steady_clock::now();
+        leaf_work(c, f);
+        c.seconds_eri += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return;
+    }
+    if (f.e_count == 0) return;
+    DevArena A(st);
+    FxLevelArgs L{};
+    L.ad = f.ad;
+    L.bc_off = f.bc_off;
+    L.bc = f.bc;
+    L.bc_parent = f.parent;
+    L.e_begin = f.e_begin;
+    L.e_count = f.e_count;
+    L.p_base = f.p_base;
+    L.nad = f.nad;
+    L.ch0 = T->d_ch0[k];
+    L.nch = T->d_nch[k];
+    L.Qsq = T->d_Qsq[k + 1];
+    L.Psq = c.Psq[k + 1];
+    L.nk1 = (int)T->levels[k + 1].sL.size();
+    L.tau2 = c.tau * c.tau;
+    const long nm = 4 * f.e_count;
+    uint8_t* mask = A.get<uint8_t>(nm);
+    long* pos = A.get<long>(nm + 1);
+    fx_launch_expand_mask(L, mask, st);
+    fx_scan_popc_u8(mask, nm, pos, scan_partial(c, A, nm), c.scan_total, st);
+    FX_HIP(hipGetLastError());
+    const long total = read1(c.scan_total, st);
+    if (total > c.cap && f.nad > 1) {
+        // chunk: split this level's ADs in two halves and traverse each
+        A.release(mask);
+        A.release(pos);
+        const int h = f.nad / 2;
+        const long mid = read1(f.bc_off + h, st);
+        Frontier f1 = f, f2 = f;
+        f1.nad = h;
+        f1.e_count = mid - f.e_begin;
+        f2.ad = f.ad + h;
+        f2.bc_off = f.bc_off + h;
+        f2.nad = f.nad - h;
+        f2.e_begin = mid;
+        f2.e_count = f.e_begin + f.e_count - mid;
+        f2.p_base = f.p_base + h;
+        if (c.stats) {
+            c.stats->chunks += 1;
+            c.stats->frontier[k] -= f.e_count;   // re-counted by the halves
+        }
+        traverse(c, k, f1);
+        traverse(c, k, f2);
+        return;
+    }
+    if (total > (1L << 31) - 1) fx_fail(FX_ERR_OOM, "a single K block pair exceeds the frontier capacity");
+    int* flag = A.get<int>(4L * f.nad);
+    long* adpos = A.get<long>(4L * f.nad + 1);
+    fx_launch_expand_adflag(L, pos, flag, st);
+    fx_scan_i32(flag, 4L * f.nad, adpos, scan_partial(c, A, 4L * f.nad), c.scan_total, st);
+    const long nads = read1(c.scan_total, st);
+    DevArena N(st);
+    Frontier g{};
+    g.ad = N.get<int2>(std::max(1L, nads));
+    g.bc_off = N.get<long>(nads + 1);
+    g.bc = N.get<int2>(std::max(1L, total));
+    g.parent = N.get<int>(std::max(1L, total));
+    g.nad = (int)nads;
+    g.e_begin = 0;
+    g.e_count = total;
+    g.p_base = 0;
+    fx_launch_expand_adwrite(L, pos, flag, adpos, g.ad, g.bc_off, total, nads, st);
+    fx_launch_expand_write(L, mask, pos, adpos, g.bc, g.parent, st);
+    FX_HIP(hipGetLastError());
+    A.release(mask);
+    A.release(pos);
+    A.release(flag);
+    A.release(adpos);
+    traverse(c, k + 1, g);
+}
+
+static void validate_exchange(const fx_tree* T, const double* P, double tau, const double* K) {
+    if (!T) fx_fail(FX_ERR_INVALID_ARG, "tree is NULL");
+    if (!P || !K) fx_fail(FX_ERR_INVALID_ARG, "P and K must be device pointers");
+    if (P == K) fx_fail(FX_ERR_INVALID_ARG, "P must not alias K");
+    if (!(tau >= 0.0) || !std::isfinite(tau)) fx_fail(FX_ERR_INVALID_ARG, "tau must be finite and >= 0");
+    if (((uintptr_t)P & 7) || ((uintptr_t)K & 7)) fx_fail(FX_ERR_INVALID_ARG, "P and K must be 8-byte aligned");
+}
+
+static void exchange_impl(const fx_tree* T, const double* P, double tau, double* K, const fx_exchange_opts* opts,
+                          fx_stats* stats, hipStream_t st) {
+    auto t0 = std::chrono::steady_clock::now();
+    validate_exchange(T, P, tau, K);
+    fx_exchange_opts o{};
+    o.precision = FX_PREC_FP64;
+    o.fp32_threshold = 1e-5;
+    o.schedule = FX_SCHED_BOUND;
+    o.alpha = 1.0;
+    o.beta = 0.0;
+    if (opts) o = *opts;
+    if (o.precision != FX_PREC_FP64 && o.precision != FX_PREC_MIXED) fx_fail(FX_ERR_INVALID_ARG, "bad precision");
+    if (o.schedule < 0 || o.schedule > 2) fx_fail(FX_ERR_INVALID_ARG, "bad schedule");
+    if (!std::isfinite(o.alpha) || !std::isfinite(o.beta)) fx_fail(FX_ERR_INVALID_ARG, "alpha/beta not finite");
+    if (o.precision == FX_PREC_MIXED && !(o.fp32_threshold >= 0.0)) fx_fail(FX_ERR_INVALID_ARG, "bad fp32_threshold");
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->levels = (int)T->levels.size();
+    }
+    const int S = T->S;
+    const long n = T->n, nn = n * n;
+    DevArena A(st);
+    ExCtx c{};
+    c.T = T;
+    c.P = P;
+    c.tau = tau;
+    c.st = st;
+    c.precision = o.precision;
+    c.thr = o.fp32_threshold;
+    c.schedule = o.schedule;
+    c.cm = o.costmodel;
+    c.cap = o.max_frontier_entries > 0 ? o.max_frontier_entries : (1L << 30);
+    c.stats = stats;
+    // density norms
+    c.Pn = A.get<double>((size_t)S * S);
+    fx_launch_pnorm(P, n, T->basis.l, T->basis.f0, S, c.Pn, st);
+    const int nl = (int)T->levels.size();
+    c.Psq.resize(nl);
+    for (int k = nl - 1; k >= 0; --k) {
+        const int nk = (int)T->levels[k].sL.size();
+        c.Psq[k] = A.get<double>((size_t)nk * nk);
+        if (k == nl - 1)
+            fx_launch_leaf_sq(c.Pn, S, T->d_sL[k], T->d_sR[k], nk, c.Psq[k], st);
+        else
+            fx_launch_level_up(c.Psq[k + 1], (int)T->levels[k + 1].sL.size(), T->d_ch0[k], T->d_nch[k], nk, c.Psq[k], st);
+    }
+    // slots
+    c.nslot = (T->lmax + 1) * (T->lmax + 1) * (o.precision == FX_PREC_MIXED ? 2 : 1);
+    c.slots = A.get<double>((size_t)c.nslot * nn);
+    fx_launch_fill(c.slots, (long)c.nslot * nn, 0.0, st);
+    c.counters = A.get<unsigned long long>(81 * 2 * 2);
+    FX_HIP(hipMemsetAsync(c.counters, 0, sizeof(unsigned long long) * 81 * 4, st));
+    c.scan_partial_cap = 1 << 16;
+    c.scan_partial = A.get<long>(c.scan_partial_cap);
+    c.scan_total = A.get<long>(1);
+    FX_HIP(hipGetLastError());
+    // root task
+    const double q0 = read1(T->d_Qsq[0], st), p0 = read1(c.Psq[0], st);
+    if ((q0 * q0) * p0 * (1.0 + 1e-12) > tau * tau) {
+        DevArena R(st);
+        Frontier f{};
+        f.ad = upload(R, std::vector<int2>{make_int2(0, 0)});
+        f.bc_off = upload(R, std::vector<long>{0, 1});
+        f.bc = upload(R, std::vector<int2>{make_int2(0, 0)});
+        f.parent = upload(R, std::vector<int>{0});
+        f.nad = 1;
+        f.e_begin = 0;
+        f.e_count = 1;
+        f.p_base = 0;
+        traverse(c, 0, f);
+    }
+    fx_launch_finalize(c.slots, c.nslot, nn, o.alpha, o.beta, K, st);
+    FX_HIP(hipGetLastError());
+    std::vector<unsigned long long> cnt(81 * 4);
+    FX_HIP(hipMemcpyAsync(cnt.data(), c.counters, sizeof(unsigned long long) * cnt.size(), hipMemcpyDeviceToHost, st));
+    FX_HIP(hipStreamSynchronize(st));
+    if (stats) {
+        for (int cls = 0; cls < 81; ++cls)
+            for (int pr = 0; pr < 2; ++pr) {
+                const unsigned long long q = cnt[(cls * 2 + pr) * 2], pq = cnt[(cls * 2 + pr) * 2 + 1];
+                stats->class_quartets[cls] += (int64_t)q;
+                stats->quartets += (int64_t)q;
+                if (pr) stats->quartets_fp32 += (int64_t)q;
+                stats->prim_quartets += (double)pq;
+                stats->flops += (double)pq * fx_class_vrr_flops[cls] + (double)q * fx_class_hrr_flops[cls];
+            }
+        stats->seconds_eri = c.seconds_eri;
+        stats->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        stats->seconds_traversal = stats->seconds_total - c.seconds_eri;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+fx_status fx_build_quadtree(const fx_shells* shells, const fx_tree_opts* opts, void* stream, fx_tree** out) {
+    return fx_guard([&] {
+        if (!out) fx_fail(FX_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        fx_tree* T = new fx_tree();
+        try {
+            build_tree(shells, opts, (hipStream_t)stream, T);
+        } catch (...) {
+            delete T;
+            throw;
+        }
+        *out = T;
+    });
+}
+
+fx_status fx_exchange_ex(const fx_tree* tree, const double* P, double tau, double* K, const fx_exchange_opts* opts,
+                         fx_stats* stats, void* stream) {
+    return fx_guard([&] { exchange_impl(tree, P, tau, K, opts, stats, (hipStream_t)stream); });
+}
+
+fx_status fx_exchange(const fx_tree* tree, const double* P, double tau, double* K, void* stream) {
+    return fx_exchange_ex(tree, P, tau, K, nullptr, nullptr, stream);
+}
+
+fx_status fx_exchange_batched(const fx_tree* const* trees, const double* const* P, double* const* K, int32_t count,
+                              double tau, const fx_exchange_opts* opts, fx_stats* stats, void* stream) {
+    return fx_guard([&] {
+        if (count < 0 || (count > 0 && (!trees || !P || !K))) fx_fail(FX_ERR_INVALID_ARG, "bad batch arrays");
+        for (int i = 0; i < count; ++i) validate_exchange(trees[i], P[i], tau, K[i]);
+        fx_stats acc{}, one{};
+        for (int i = 0; i < count; ++i) {
+            exchange_impl(trees[i], P[i], tau, K[i], opts, stats ? &one : nullptr, (hipStream_t)stream);
+            if (stats) {
+                acc.levels = std::max(acc.levels, one.levels);
+                for (int k = 0; k < FX_STATS_MAX_LEVELS; ++k) acc.frontier[k] += one.frontier[k];
+                acc.leaf_items += one.leaf_items;
+                acc.units += one.units;
+                acc.quartets += one.quartets;
+                acc.quartets_fp32 += one.quartets_fp32;
+                for (int k = 0; k < 81; ++k) acc.class_quartets[k] += one.class_quartets[k];
+                acc.prim_quartets += one.prim_quartets;
+                acc.flops += one.flops;
+                acc.chunks += one.chunks;
+                acc.seconds_traversal += one.seconds_traversal;
+                acc.seconds_eri += one.seconds_eri;
+                acc.seconds_total += one.seconds_total;
+            }
+        }
+        if (stats) *stats = acc;
+    });
+}
+
+int32_t fx_nbf(const fx_tree* tree) { return tree ? tree->n : -1; }
+int32_t fx_nshell(const fx_tree* tree) { return tree ? tree->S : -1; }
+
+fx_status fx_tree_perm(const fx_tree* tree, int32_t* perm) {
+    return fx_guard([&] {
+        if (!tree || !perm) fx_fail(FX_ERR_INVALID_ARG, "NULL argument");
+        for (int i = 0; i < tree->S; ++i) perm[i] = tree->order[i];
+    });
+}
+
+int32_t fx_tree_levels(const fx_tree* tree, int64_t* nodes) {
+    if (!tree) return -1;
+    if (nodes)
+        for (size_t k = 0; k < tree->levels.size(); ++k) nodes[k] = (int64_t)tree->levels[k].sL.size();
+    return (int32_t)tree->levels.size();
+}
+
+fx_status fx_tree_schwarz(const fx_tree* tree, double* Qh) {
+    return fx_guard([&] {
+        if (!tree || !Qh) fx_fail(FX_ERR_INVALID_ARG, "NULL argument");
+        const int S = tree->S;
+        std::vector<double> q((size_t)S * S);
+        FX_HIP(hipMemcpy(q.data(), tree->basis.Qn, sizeof(double) * q.size(), hipMemcpyDeviceToHost));
+        for (int a = 0; a < S; ++a)
+            for (int b = 0; b < S; ++b) Qh[(size_t)tree->order[a] * S + tree->order[b]] = q[(size_t)a * S + b];
+    });
+}
+
+void fx_tree_free(fx_tree* tree) { delete tree; }
+
+fx_status fx_set_allocator(fx_alloc_fn alloc, fx_free_fn free_, void* ctx) {
+    return fx_guard([&] {
+        if ((alloc == nullptr) != (free_ == nullptr)) fx_fail(FX_ERR_INVALID_ARG, "give both callbacks or neither");
+        g_alloc = alloc;
+        g_free = free_;
+        g_alloc_ctx = ctx;
+    });
+}
+
+const char* fx_status_string(fx_status s) {
+    switch (s) {
+        case FX_OK: return "FX_OK";
+        case FX_ERR_INVALID_ARG: return "FX_ERR_INVALID_ARG";
+        case FX_ERR_UNSUPPORTED: return "FX_ERR_UNSUPPORTED";
+        case FX_ERR_OOM: return "FX_ERR_OOM";
+        case FX_ERR_HIP: return "FX_ERR_HIP";
+        case FX_ERR_INTERNAL: return "FX_ERR_INTERNAL";
+    }
+    return "FX_ERR_UNKNOWN";
+}
+
+const char* fx_last_error_message(void) { return g_last_error.c_str(); }
+
+// Host-only planning (no device work): the tree order and the bisection
+// levels.  perm[nshell]; nodes: 4 ints per node (level, first shell, end
+// shell, children) for all levels, capacity given in node_cap.  Returns the
+// number of levels through *nlevels and the node count through *nnodes.
+fx_status fx_plan_tree(const fx_shells* shells, const fx_tree_opts* opts, int32_t* perm, int32_t* nlevels,
+                       int32_t* nodes, int64_t node_cap, int64_t* nnodes) {
+    return fx_guard([&] {
+        validate_shells(shells);
+        Plan P = make_plan(shells, opts);
+        if (perm)
+            for (int i = 0; i < shells->nshell; ++i) perm[i] = P.order[i];
+        if (nlevels) *nlevels = (int32_t)P.levels.size();
+        int64_t k = 0;
+        for (size_t lv = 0; lv < P.levels.size(); ++lv)
+            for (size_t i = 0; i < P.levels[lv].sL.size(); ++i, ++k)
+                if (nodes && k < node_cap) {
+                    nodes[4 * k] = (int32_t)lv;
+                    nodes[4 * k + 1] = P.levels[lv].sL[i];
+                    nodes[4 * k + 2] = P.levels[lv].sR[i];
+                    nodes[4 * k + 3] = P.levels[lv].nch[i];
+                }
+        if (nnodes) *nnodes = k;
+    });
+}
+
+}  // extern "C"

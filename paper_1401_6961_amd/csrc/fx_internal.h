@@ -1,0 +1,54 @@
+// Internal structures shared by the host planner and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define FX_CLASS_WAVES 4          // waves (work units) per class-kernel workgroup
+
+// Boys table: F_j(T_i), T_i = i / 32, i = 0..FX_BOYS_NROW-1, j = 0..FX_BOYS_NCOL-1
+#define FX_BOYS_DT (1.0 / 32.0)
+#define FX_BOYS_INV_DT 32.0
+#define FX_BOYS_TMAX 40.0
+#define FX_BOYS_NCOL 15           // highest m (8) + 6 Taylor terms + 1
+#define FX_BOYS_NROW 1282
+
+enum { FX_MODE_ALL = 0, FX_MODE_MIXED_HI = 1, FX_MODE_MIXED_LO = 2 };
+
+// Basis in the tree's shell order (device pointers).
+struct FxDevBasis {
+    int nshell, nbf;
+    const int* l;         // [S]
+    const int* nprim;     // [S]
+    const int* pofs;      // [S] first primitive
+    const int* f0;        // [S] first function, CALLER order (rows/cols of P and K)
+    const double* xyz;    // [S*3] bohr
+    const double* exps;   // [sum nprim]
+    const double* coefs;  // [sum nprim] normalised radial weights
+    const double* Qn;     // [S*S] ||Q_ab||_F
+    const int* leaf_lofs; // [nleaf*4] per leaf: offsets of its l=0,1,2 shell lists, then end
+    const int* leaf_lsh;  // shell indices grouped per leaf and l
+};
+
+// Arguments of one class kernel launch.
+struct FxClassArgs {
+    FxDevBasis basis;
+    const double* boys;
+    const double* P;
+    long n;
+    const double* Pn;                 // [S*S] shell-level ||P_bc||_F
+    const int* units;                 // [3*nunits] (item, a, d)
+    const int* order;                 // schedule permutation of units, or null
+    long nunits;
+    const long* bc_off;               // per leaf item: offsets into bc
+    const int2* bc;                   // (B, C) leaf nodes
+    double tau, thr;
+    int mode;                         // FX_MODE_*
+    double* kslot;                    // n*n slot for this (lb, lc, precision)
+    unsigned long long* counters;     // computed quartets (nullable)
+};
+
+// Launchers defined in the generated class files.
+#define FX_DECLARE_LAUNCH(cls) void fx_launch_##cls(int prec32, FxClassArgs A, int grid, hipStream_t st);
+typedef void (*fx_class_launcher)(int, FxClassArgs, int, hipStream_t);
+void fx_launch_schwarz(FxDevBasis B, const double* boys, const int2* pairs, long npairs, double* Qn,
+                       hipStream_t st);

@@ -1,0 +1,444 @@
+#!/usr/bin/env python3
+"""Code generator for the shell-quartet ERI + exchange-contraction routines.
+
+For every ordered angular-momentum class (la lb|lc ld), la..ld in {s,p,d},
+this emits a device routine that evaluates one contracted shell quartet by
+the Head-Gordon-Pople scheme the paper's implementation uses (Section V):
+
+  1. per primitive quartet: Boys function F_m(T) (FP64), then the
+     Obara-Saika vertical recursion (VRR) building [e0|f0]^(0) from
+     [00|00]^(m), first on the bra centre (OS), then transferring angular
+     momentum to the ket centre;
+  2. the primitive sum of [e0|f0];
+  3. the horizontal recursion (HRR) on the contracted quantities,
+     (a, b+1_i| = (a+1_i, b| + AB_i (a b|, first on the bra, then the ket;
+  4. the exchange contraction of Eq. (6) for this quartet,
+     K_{mu sig} += sum_{nu lam} (mu nu|lam sig) P_{nu lam}, accumulated in
+     FP64 registers.
+
+Each class is oriented internally so that the VRR/HRR run on the centre of
+higher angular momentum of each pair, and with the bra/ket order that gives
+fewer floating-point operations; the external (a,b,c,d) roles of the
+exchange contraction are mapped back when the contraction is emitted.
+
+The routine is emitted in FP64 and in FP32 (VRR/HRR/primitive sum in FP32,
+Boys, pair geometry and all K accumulation in FP64).  The generator also
+counts the floating-point operations it emits, per primitive quartet and
+per contracted quartet, which the library reports as algorithmic flops.
+"""
+from __future__ import annotations
+
+import itertools
+import os
+import sys
+
+LNAME = "spd"
+
+
+def cart(l):
+    """Cartesian exponent triples of shell l, lexicographic (x^l first)."""
+    out = []
+    for i in range(l, -1, -1):
+        for j in range(l - i, -1, -1):
+            out.append((i, j, l - i - j))
+    return out
+
+
+def comp_factor_sq(t):
+    """sqrt((2l-1)!! / ((2i-1)!!(2j-1)!!(2k-1)!!)) squared -> ratio as float."""
+    def df(n):
+        r = 1
+        while n > 1:
+            r *= n
+            n -= 2
+        return r
+    l = sum(t)
+    return df(2 * l - 1) / (df(2 * t[0] - 1) * df(2 * t[1] - 1) * df(2 * t[2] - 1))
+
+
+def comp_factor(t):
+    return comp_factor_sq(t) ** 0.5
+
+
+def sub(t, i, k=1):
+    return tuple(t[j] - (k if j == i else 0) for j in range(3))
+
+
+def add(t, i, k=1):
+    return tuple(t[j] + (k if j == i else 0) for j in range(3))
+
+
+def argmax_dir(t):
+    best = 0
+    for i in range(3):
+        if t[i] > t[best]:
+            best = i
+    return best
+
+
+XYZ = "xyz"
+
+
+class Emitter:
+    """Emits straight-line code for one class; counts flops."""
+
+    def __init__(self, real):
+        self.real = real
+        self.lines = []
+        self.names = {}
+        self.flops = 0
+        self.counter = 0
+
+    def new(self, prefix):
+        self.counter += 1
+        return f"{prefix}{self.counter}"
+
+    def emit(self, s):
+        self.lines.append(s)
+
+
+class VRR:
+    """Memoised OS/HGP vertical recursion for [e0|f0]^(m)."""
+
+    def __init__(self, em):
+        self.em = em
+        self.memo = {}
+
+    def get(self, e, f, m):
+        if min(e) < 0 or min(f) < 0:
+            return None
+        key = (e, f, m)
+        if key in self.memo:
+            return self.memo[key]
+        em = self.em
+        if sum(e) == 0 and sum(f) == 0:
+            name = f"s{m}"        # base, defined by the caller: pref * F_m
+            self.memo[key] = name
+            return name
+        terms = []
+        if sum(f) == 0:
+            # [e+1_i|0]^(m) = PA_i [e]^(m) + WP_i [e]^(m+1) + e_i/(2p) ([e-1_i]^(m) - rho/p [e-1_i]^(m+1))
+            i = argmax_dir(e)
+            e1 = sub(e, i)
+            k = e1[i]
+            a0 = self.get(e1, f, m)
+            a1 = self.get(e1, f, m + 1)
+            expr = f"PA{XYZ[i]} * {a0} + WP{XYZ[i]} * {a1}"
+            fl = 3
+            if k > 0:
+                b0 = self.get(sub(e1, i), f, m)
+                b1 = self.get(sub(e1, i), f, m + 1)
+                expr += f" + {k}.0f * (oo2p * {b0} - oo2p_rp * {b1})" if em.real == "float" else \
+                    f" + {k}.0 * (oo2p * {b0} - oo2p_rp * {b1})"
+                fl += 5
+        else:
+            # [e|f+1_i]^(m) = QC_i [e|f]^(m) + WQ_i [e|f]^(m+1)
+            #   + f_i/(2q) ([e|f-1_i]^(m) - rho/q [e|f-1_i]^(m+1)) + e_i/(2(p+q)) [e-1_i|f]^(m+1)
+            i = argmax_dir(f)
+            f1 = sub(f, i)
+            k = f1[i]
+            a0 = self.get(e, f1, m)
+            a1 = self.get(e, f1, m + 1)
+            expr = f"QC{XYZ[i]} * {a0} + WQ{XYZ[i]} * {a1}"
+            fl = 3
+            suf = ".0f" if em.real == "float" else ".0"
+            if k > 0:
+                b0 = self.get(e, sub(f1, i), m)
+                b1 = self.get(e, sub(f1, i), m + 1)
+                expr += f" + {k}{suf} * (oo2q * {b0} - oo2q_rq * {b1})"
+                fl += 5
+            if e[i] > 0:
+                c1 = self.get(sub(e, i), f1, m + 1)
+                expr += f" + {e[i]}{suf} * oo2pq * {c1}" if e[i] > 1 else f" + oo2pq * {c1}"
+                fl += 2 if e[i] == 1 else 3
+        name = em.new("v")
+        em.emit(f"const {em.real} {name} = {expr};")
+        em.flops += fl
+        self.memo[key] = name
+        return name
+
+
+class HRR:
+    """Memoised horizontal recursion on contracted [e0|f0] = C[e][f]."""
+
+    def __init__(self, em, cname):
+        self.em = em
+        self.cname = cname    # function (e, f) -> accumulator expression
+        self.memo = {}
+
+    def bra(self, a, b, f):
+        key = ("b", a, b, f)
+        if key in self.memo:
+            return self.memo[key]
+        if sum(b) == 0:
+            name = self.cname(a, f)
+            self.memo[key] = name
+            return name
+        i = argmax_dir(b)
+        b1 = sub(b, i)
+        x = self.bra(add(a, i), b1, f)
+        y = self.bra(a, b1, f)
+        name = self.em.new("h")
+        self.em.emit(f"const {self.em.real} {name} = {x} + AB{XYZ[i]}_ * {y};")
+        self.em.flops += 2
+        self.memo[key] = name
+        return name
+
+    def full(self, a, b, c, d):
+        key = ("k", a, b, c, d)
+        if key in self.memo:
+            return self.memo[key]
+        if sum(d) == 0:
+            name = self.bra(a, b, c)
+            self.memo[key] = name
+            return name
+        i = argmax_dir(d)
+        d1 = sub(d, i)
+        x = self.full(a, b, add(c, i), d1)
+        y = self.full(a, b, c, d1)
+        name = self.em.new("k")
+        self.em.emit(f"const {self.em.real} {name} = {x} + CD{XYZ[i]}_ * {y};")
+        self.em.flops += 2
+        self.memo[key] = name
+        return name
+
+
+def orientation(la, lb, lc, ld):
+    """Internal order of the four external roles (0=a,1=b,2=c,3=d):
+    (x1 x2|x3 x4) with l(x1) >= l(x2), l(x3) >= l(x4).  The bra/ket order is
+    chosen by trying both and keeping the one with fewer emitted flops
+    (VRR per primitive quartet plus HRR per contracted quartet)."""
+    ls = (la, lb, lc, ld)
+    bra = (0, 1) if la >= lb else (1, 0)
+    ket = (2, 3) if lc >= ld else (3, 2)
+    best = None
+    for o in (bra + ket, ket + bra):
+        L = [ls[x] for x in o]
+        body = build_body("double", L)
+        hrr = body["hrr"]
+        comps = [cart(l) for l in L]
+        for t in itertools.product(*comps):
+            hrr.full(*t)
+        cost = body["vem"].flops + body["hem"].flops
+        if best is None or cost < best[0]:
+            best = (cost, o)
+    return best[1]
+
+
+def build_body(real, L):
+    """VRR (emitted inside the primitive loop) and HRR (after it) for the
+    internal angular momenta L = (l1,l2,l3,l4)."""
+    l1, l2, l3, l4 = L
+    vem = Emitter(real)
+    vrr = VRR(vem)
+    targets = []
+    for le in range(l1, l1 + l2 + 1):
+        for e in cart(le):
+            for lf in range(l3, l3 + l4 + 1):
+                for f in cart(lf):
+                    targets.append((e, f))
+    tnames = [vrr.get(e, f, 0) for (e, f) in targets]
+    idx = {t: k for k, t in enumerate(targets)}
+    hem = Emitter(real)
+    hrr = HRR(hem, lambda e, f: f"C[{idx[(e, f)]}]")
+    return dict(vem=vem, targets=targets, tnames=tnames, hem=hem, hrr=hrr)
+
+
+def gen_class(la, lb, lc, ld, real, diag=False):
+    """Return (code, flops_per_prim, flops_per_contracted) for one class.
+
+    diag=True emits the Schwarz routine for (ab|ab) (la==lc, lb==ld):
+    the sum over mu, nu of max(0, (mu nu|mu nu))."""
+    ls = (la, lb, lc, ld)
+    o = orientation(la, lb, lc, ld) if not diag else ((0, 1, 2, 3) if la >= lb else (1, 0, 3, 2))
+    L = [ls[x] for x in o]
+    body = build_body(real, L)
+    vem, targets, tnames, hem, hrr = body["vem"], body["targets"], body["tnames"], body["hem"], body["hrr"]
+    Lsum = sum(L)
+    suffix = "f" if real == "float" else ""
+    # external component lists
+    comps = [cart(l) for l in ls]
+    # integral over (mu nu|lam sig) external -> internal component tuple
+    def integral(mu, nu, lam, sig):
+        ext = (mu, nu, lam, sig)
+        t = [None] * 4
+        for pos, role in enumerate(o):
+            t[pos] = ext[role]
+        return hrr.full(t[0], t[1], t[2], t[3])
+
+    out = []
+    w = out.append
+    cls = f"{LNAME[la]}{LNAME[lb]}{LNAME[lc]}{LNAME[ld]}"
+    prec = "f32" if real == "float" else "f64"
+    fname = f"eri_{'diag_' if diag else ''}{cls}_{prec}"
+    # centres: external a,b,c,d -> X[role]
+    w(f"// class ({LNAME[la]}{LNAME[lb]}|{LNAME[lc]}{LNAME[ld]}) {prec}; internal order "
+      f"({'abcd'[o[0]]}{'abcd'[o[1]]}|{'abcd'[o[2]]}{'abcd'[o[3]]})")
+    if diag:
+        w(f"__device__ __forceinline__ double {fname}(const FxShellRef& s0, const FxShellRef& s1,")
+        w(f"    const double* __restrict__ exps, const double* __restrict__ coefs, const double* __restrict__ boys_tab) {{")
+        w("  const FxShellRef& ra = s0; const FxShellRef& rb = s1; const FxShellRef& rc = s0; const FxShellRef& rd = s1;")
+    else:
+        w(f"__device__ __forceinline__ void {fname}(const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc,")
+        w(f"    const FxShellRef& rd, const double* __restrict__ exps, const double* __restrict__ coefs,")
+        w(f"    const double* __restrict__ boys_tab, const double* __restrict__ Pmat, long ldp, double* __restrict__ kacc) {{")
+    roles = ["ra", "rb", "rc", "rd"]
+    x = [roles[r] for r in o]
+    w(f"  const FxShellRef& x1 = {x[0]}; const FxShellRef& x2 = {x[1]}; const FxShellRef& x3 = {x[2]}; const FxShellRef& x4 = {x[3]};")
+    nacc = len(targets)
+    w(f"  {real} C[{nacc}];")
+    w(f"  #pragma unroll")
+    w(f"  for (int k = 0; k < {nacc}; ++k) C[k] = 0;")
+    w("  const double ABx = x1.x - x2.x, ABy = x1.y - x2.y, ABz = x1.z - x2.z;")
+    w("  const double CDx = x3.x - x4.x, CDy = x3.y - x4.y, CDz = x3.z - x4.z;")
+    w("  const double AB2 = ABx * ABx + ABy * ABy + ABz * ABz;")
+    w("  const double CD2 = CDx * CDx + CDy * CDy + CDz * CDz;")
+    w("  for (int i1 = 0; i1 < x1.nprim; ++i1) {")
+    w("    const double a1 = exps[x1.pofs + i1], c1 = coefs[x1.pofs + i1];")
+    w("    for (int i2 = 0; i2 < x2.nprim; ++i2) {")
+    w("      const double a2 = exps[x2.pofs + i2];")
+    w("      const double p = a1 + a2, op = 1.0 / p;")
+    w("      const double Kab = c1 * coefs[x2.pofs + i2] * exp(-a1 * a2 * op * AB2);")
+    w("      const double Px = (a1 * x1.x + a2 * x2.x) * op, Py = (a1 * x1.y + a2 * x2.y) * op, Pz = (a1 * x1.z + a2 * x2.z) * op;")
+    w("      for (int i3 = 0; i3 < x3.nprim; ++i3) {")
+    w("        const double a3 = exps[x3.pofs + i3], c3 = coefs[x3.pofs + i3];")
+    w("        for (int i4 = 0; i4 < x4.nprim; ++i4) {")
+    w("          const double a4 = exps[x4.pofs + i4];")
+    w("          const double q = a3 + a4, oq = 1.0 / q;")
+    w("          const double Kcd = c3 * coefs[x4.pofs + i4] * exp(-a3 * a4 * oq * CD2);")
+    w("          const double Qx = (a3 * x3.x + a4 * x4.x) * oq, Qy = (a3 * x3.y + a4 * x4.y) * oq, Qz = (a3 * x3.z + a4 * x4.z) * oq;")
+    w("          const double ppq = p + q, oppq = 1.0 / ppq, rho = p * q * oppq;")
+    w("          const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;")
+    w("          const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);")
+    w("          const double pref = FX_TWO_PI_POW_2_5 * op * oq * sqrt(oppq) * Kab * Kcd;")
+    w(f"          double F[{Lsum + 1}];")
+    w(f"          fx_boys<{Lsum}>(T, boys_tab, F);")
+    for m in range(Lsum + 1):
+        w(f"          const {real} s{m} = ({real})(pref * F[{m}]);")
+    if Lsum > 0:
+        w("          const double Wx = (p * Px + q * Qx) * oppq, Wy = (p * Py + q * Qy) * oppq, Wz = (p * Pz + q * Qz) * oppq;")
+        for c in "xyz":
+            w(f"          const {real} PA{c} = ({real})(P{c} - x1.{c}), WP{c} = ({real})(W{c} - P{c});")
+            w(f"          const {real} QC{c} = ({real})(Q{c} - x3.{c}), WQ{c} = ({real})(W{c} - Q{c});")
+        w(f"          const {real} oo2p = ({real})(0.5 * op), oo2q = ({real})(0.5 * oq), oo2pq = ({real})(0.5 * oppq);")
+        w(f"          const {real} oo2p_rp = ({real})(0.5 * op * rho * op), oo2q_rq = ({real})(0.5 * oq * rho * oq);")
+        w("          (void)PAx; (void)PAy; (void)PAz; (void)WPx; (void)WPy; (void)WPz;")
+        w("          (void)QCx; (void)QCy; (void)QCz; (void)WQx; (void)WQy; (void)WQz;")
+        w("          (void)oo2p; (void)oo2q; (void)oo2pq; (void)oo2p_rp; (void)oo2q_rq;")
+    for line in vem.lines:
+        w("          " + line)
+    for k, nm in enumerate(tnames):
+        w(f"          C[{k}] += {nm};")
+    w("        }")
+    w("      }")
+    w("    }")
+    w("  }")
+    # HRR + contraction
+    w(f"  const {real} ABx_ = ({real})ABx, ABy_ = ({real})ABy, ABz_ = ({real})ABz;")
+    w(f"  const {real} CDx_ = ({real})CDx, CDy_ = ({real})CDy, CDz_ = ({real})CDz;")
+    w("  (void)ABx_; (void)ABy_; (void)ABz_; (void)CDx_; (void)CDy_; (void)CDz_;")
+    if diag:
+        # sum_{mu nu} max(0, (mu nu|mu nu)); internal (x1 x2|x1 x2) is the same quartet
+        terms = []
+        for mu in comps[0]:
+            for nu in comps[1]:
+                terms.append(integral(mu, nu, mu, nu))
+        for line in hem.lines:
+            w("  " + line)
+        w("  double s2 = 0.0;")
+        # the same component-normalisation factors apply: (mu nu|mu nu) scales by (f_mu f_nu)^2
+        for (mu, nu), tn in zip(itertools.product(comps[0], comps[1]), terms):
+            fac = comp_factor_sq(mu) * comp_factor_sq(nu)
+            w(f"  {{ const double v = (double){tn} * {fac!r}; s2 += v > 0.0 ? v : 0.0; }}")
+        w("  return s2;")
+        w("}")
+        return "\n".join(out), vem.flops, hem.flops
+    # contraction: kacc[mu*nd + sig] += sum_{nu,lam} I * (f_nu f_lam P_{nu lam})
+    nb, nc, nd = len(comps[1]), len(comps[2]), len(comps[3])
+    ints = {}
+    for im, mu in enumerate(comps[0]):
+        for jn, nu in enumerate(comps[1]):
+            for kl, lam in enumerate(comps[2]):
+                for ls_, sig in enumerate(comps[3]):
+                    ints[(im, jn, kl, ls_)] = integral(mu, nu, lam, sig)
+    for line in hem.lines:
+        w("  " + line)
+    cflops = 0
+    for jn, nu in enumerate(comps[1]):
+        for kl, lam in enumerate(comps[2]):
+            fac = comp_factor(nu) * comp_factor(lam)
+            pv = f"pv{jn}_{kl}"
+            if abs(fac - 1.0) < 1e-15:
+                w(f"  const double {pv} = Pmat[{jn} * ldp + {kl}];")
+            else:
+                w(f"  const double {pv} = Pmat[{jn} * ldp + {kl}] * {fac!r};")
+                cflops += 1
+            for im in range(len(comps[0])):
+                for ls_ in range(nd):
+                    w(f"  kacc[{im * nd + ls_}] += (double){ints[(im, jn, kl, ls_)]} * {pv};")
+                    cflops += 2
+    w("}")
+    return "\n".join(out), vem.flops, hem.flops + cflops
+
+
+def classes():
+    return list(itertools.product(range(3), repeat=4))
+
+
+def main(outdir):
+    os.makedirs(outdir, exist_ok=True)
+    stats = []
+    for (la, lb, lc, ld) in classes():
+        cls = f"{LNAME[la]}{LNAME[lb]}{LNAME[lc]}{LNAME[ld]}"
+        parts = []
+        for real in ("double", "float"):
+            code, fp, fc = gen_class(la, lb, lc, ld, real)
+            parts.append(code)
+            if real == "double":
+                stats.append((cls, fp, fc))
+        src = ["// Generated by gen_eri.py -- do not edit.", '#include "fx_eri_common.h"', ""]
+        src += parts
+        src.append(f'FX_DEFINE_CLASS_KERNELS({la}, {lb}, {lc}, {ld}, {cls})')
+        path = os.path.join(outdir, f"eri_{cls}.hip")
+        new = "\n".join(src) + "\n"
+        if not os.path.exists(path) or open(path).read() != new:
+            open(path, "w").write(new)
+    # Schwarz (diagonal) routines: (ab|ab) for the 9 ordered pair types
+    src = ["// Generated by gen_eri.py -- do not edit.", '#include "fx_eri_common.h"', ""]
+    for la in range(3):
+        for lb in range(3):
+            code, _, _ = gen_class(la, lb, la, lb, "double", diag=True)
+            src.append(code)
+    src.append("FX_DEFINE_SCHWARZ_KERNEL()")
+    path = os.path.join(outdir, "eri_schwarz.hip")
+    new = "\n".join(src) + "\n"
+    if not os.path.exists(path) or open(path).read() != new:
+        open(path, "w").write(new)
+    # dispatch table
+    names = [f"{LNAME[a]}{LNAME[b]}{LNAME[c]}{LNAME[d]}" for (a, b, c, d) in classes()]
+    lines = ["// Generated by gen_eri.py -- do not edit.", "#pragma once", '#include "fx_internal.h"']
+    lines += [f"FX_DECLARE_LAUNCH({n})" for n in names]
+    lines.append("// indexed by ((la*3+lb)*3+lc)*3+ld")
+    lines.append("static const fx_class_launcher fx_class_table[81] = {" + ", ".join(f"fx_launch_{n}" for n in names) + "};")
+    path = os.path.join(outdir, "eri_table.h")
+    new = "\n".join(lines) + "\n"
+    if not os.path.exists(path) or open(path).read() != new:
+        open(path, "w").write(new)
+    # flop table (FP64 emission; FP32 emits the same operations)
+    lines = ["// Generated by gen_eri.py -- do not edit.",
+             "// Flops emitted per primitive quartet (VRR) and per contracted quartet (HRR + contraction),",
+             "// indexed by ((la*3+lb)*3+lc)*3+ld.  Boys, pair set-up and exp are counted separately.",
+             "#pragma once",
+             "static const int fx_class_vrr_flops[81] = {" + ", ".join(str(s[1]) for s in stats) + "};",
+             "static const int fx_class_hrr_flops[81] = {" + ", ".join(str(s[2]) for s in stats) + "};"]
+    path = os.path.join(outdir, "eri_flops.h")
+    new = "\n".join(lines) + "\n"
+    if not os.path.exists(path) or open(path).read() != new:
+        open(path, "w").write(new)
+    return stats
+
+
+if __name__ == "__main__":
+    st = main(sys.argv[1] if len(sys.argv) > 1 else os.path.join(os.path.dirname(os.path.abspath(__file__)), "gen"))
+    for s in st:
+        print(*s)

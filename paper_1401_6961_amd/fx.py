@@ -1,0 +1,271 @@
+"""Python binding of libfx (ctypes): argument marshalling only.
+
+Every step of the exchange build runs in the library's HIP kernels; PyTorch
+is used only for device memory (float64 CUDA tensors) and streams.  The
+function names mirror the C ABI in include/fx.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfx.so")
+_lib = None
+
+FX_PREC_FP64, FX_PREC_MIXED = 0, 1
+FX_SCHED_BOUND, FX_SCHED_MLP, FX_SCHED_NONE = 0, 1, 2
+
+
+class FxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status_string(status)}: {msg}")
+        self.status = status
+
+
+class fx_shells(ctypes.Structure):
+    _fields_ = [("nshell", ctypes.c_int32), ("l", ctypes.POINTER(ctypes.c_int32)),
+                ("nprim", ctypes.POINTER(ctypes.c_int32)), ("center", ctypes.POINTER(ctypes.c_double)),
+                ("exps", ctypes.POINTER(ctypes.c_double)), ("coefs", ctypes.POINTER(ctypes.c_double))]
+
+
+class fx_tree_opts(ctypes.Structure):
+    _fields_ = [("leaf_max_functions", ctypes.c_int32), ("ordering", ctypes.c_int32)]
+
+
+class fx_exchange_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("fp32_threshold", ctypes.c_double),
+                ("schedule", ctypes.c_int32), ("costmodel", ctypes.c_void_p),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("max_frontier_entries", ctypes.c_int64)]
+
+
+class fx_stats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("frontier", ctypes.c_int64 * 32),
+                ("leaf_items", ctypes.c_int64), ("units", ctypes.c_int64),
+                ("quartets", ctypes.c_int64), ("quartets_fp32", ctypes.c_int64),
+                ("class_quartets", ctypes.c_int64 * 81), ("prim_quartets", ctypes.c_double),
+                ("flops", ctypes.c_double), ("chunks", ctypes.c_int32),
+                ("seconds_traversal", ctypes.c_double), ("seconds_eri", ctypes.c_double),
+                ("seconds_total", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"levels": self.levels, "frontier": list(self.frontier)[: self.levels],
+                "leaf_items": self.leaf_items, "units": self.units, "quartets": self.quartets,
+                "quartets_fp32": self.quartets_fp32,
+                "class_quartets": np.array(self.class_quartets, dtype=np.int64).reshape(3, 3, 3, 3),
+                "prim_quartets": self.prim_quartets, "flops": self.flops, "chunks": self.chunks,
+                "seconds_traversal": self.seconds_traversal, "seconds_eri": self.seconds_eri,
+                "seconds_total": self.seconds_total}
+
+
+EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_batched", "fx_nbf", "fx_nshell",
+            "fx_tree_perm", "fx_tree_levels", "fx_tree_schwarz", "fx_tree_free", "fx_set_allocator",
+            "fx_status_string", "fx_last_error_message", "fx_plan_tree", "fx_hilbert_key3"]
+
+
+def lib():
+    """Load libfx.so; raises if the HIP library has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libfx.so not found at {LIB_PATH}: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.fx_build_quadtree.argtypes = [ctypes.POINTER(fx_shells), ctypes.POINTER(fx_tree_opts), vp,
+                                    ctypes.POINTER(vp)]
+    L.fx_exchange.argtypes = [vp, vp, dbl, vp, vp]
+    L.fx_exchange_ex.argtypes = [vp, vp, dbl, vp, ctypes.POINTER(fx_exchange_opts), ctypes.POINTER(fx_stats), vp]
+    L.fx_exchange_batched.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl,
+                                      ctypes.POINTER(fx_exchange_opts), ctypes.POINTER(fx_stats), vp]
+    for f in ("fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_batched", "fx_tree_perm",
+              "fx_tree_schwarz", "fx_set_allocator", "fx_plan_tree"):
+        getattr(L, f).restype = ctypes.c_int
+    L.fx_nbf.argtypes = [vp]
+    L.fx_nbf.restype = i32
+    L.fx_nshell.argtypes = [vp]
+    L.fx_nshell.restype = i32
+    L.fx_tree_perm.argtypes = [vp, ctypes.POINTER(i32)]
+    L.fx_tree_levels.argtypes = [vp, ctypes.POINTER(i64)]
+    L.fx_tree_levels.restype = i32
+    L.fx_tree_schwarz.argtypes = [vp, ctypes.POINTER(dbl)]
+    L.fx_tree_free.argtypes = [vp]
+    L.fx_tree_free.restype = None
+    L.fx_status_string.argtypes = [ctypes.c_int]
+    L.fx_status_string.restype = ctypes.c_char_p
+    L.fx_last_error_message.restype = ctypes.c_char_p
+    L.fx_plan_tree.argtypes = [ctypes.POINTER(fx_shells), ctypes.POINTER(fx_tree_opts), ctypes.POINTER(i32),
+                               ctypes.POINTER(i32), ctypes.POINTER(i32), i64, ctypes.POINTER(i64)]
+    L.fx_hilbert_key3.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, i32]
+    L.fx_hilbert_key3.restype = ctypes.c_uint64
+    _lib = L
+    return L
+
+
+def status_string(st):
+    return lib().fx_status_string(st).decode()
+
+
+def _check(st):
+    if st != 0:
+        raise FxError(st, lib().fx_last_error_message().decode())
+
+
+class _ShellArrays:
+    """Keeps the numpy arrays alive while the C struct points at them."""
+
+    def __init__(self, l, nprim, center, exps, coefs):
+        self.l = np.ascontiguousarray(l, np.int32)
+        self.nprim = np.ascontiguousarray(nprim, np.int32)
+        self.center = np.ascontiguousarray(center, np.float64).reshape(-1)
+        self.exps = np.ascontiguousarray(exps, np.float64)
+        self.coefs = np.ascontiguousarray(coefs, np.float64)
+        P = ctypes.POINTER
+        self.s = fx_shells(len(self.l), self.l.ctypes.data_as(P(ctypes.c_int32)),
+                           self.nprim.ctypes.data_as(P(ctypes.c_int32)),
+                           self.center.ctypes.data_as(P(ctypes.c_double)),
+                           self.exps.ctypes.data_as(P(ctypes.c_double)),
+                           self.coefs.ctypes.data_as(P(ctypes.c_double)))
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_matrix(x, n, name):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if tuple(x.shape) != (n, n) or not x.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous ({n}, {n}) tensor")
+
+
+class Tree:
+    """Owning handle of an fx_tree (see fx_build_quadtree)."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def nbf(self):
+        return lib().fx_nbf(self._h)
+
+    @property
+    def nshell(self):
+        return lib().fx_nshell(self._h)
+
+    def perm(self):
+        out = np.zeros(self.nshell, np.int32)
+        _check(lib().fx_tree_perm(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out
+
+    def levels(self):
+        out = np.zeros(32, np.int64)
+        n = lib().fx_tree_levels(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        return out[:n]
+
+    def schwarz(self):
+        S = self.nshell
+        out = np.zeros(S * S)
+        _check(lib().fx_tree_schwarz(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out.reshape(S, S)
+
+    def free(self):
+        if self._h:
+            lib().fx_tree_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def fx_build_quadtree(l, nprim, center, exps, coefs, leaf_max_functions=10, ordering=0, stream=None) -> Tree:
+    sh = _ShellArrays(l, nprim, center, exps, coefs)
+    opts = fx_tree_opts(int(leaf_max_functions), int(ordering))
+    h = ctypes.c_void_p()
+    _check(lib().fx_build_quadtree(ctypes.byref(sh.s), ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(h)))
+    return Tree(h.value)
+
+
+def build_quadtree_from(system, **kw) -> Tree:
+    """Convenience: a synthetic.System-like object with l, nprim, center, exps, coefs."""
+    return fx_build_quadtree(system.l, system.nprim, system.center, system.exps, system.coefs, **kw)
+
+
+def make_opts(precision=FX_PREC_FP64, fp32_threshold=1e-5, schedule=FX_SCHED_BOUND, costmodel=None, alpha=1.0,
+              beta=0.0, max_frontier_entries=0):
+    return fx_exchange_opts(int(precision), float(fp32_threshold), int(schedule),
+                            ctypes.c_void_p(costmodel.handle if costmodel is not None else None),
+                            float(alpha), float(beta), int(max_frontier_entries))
+
+
+def fx_exchange(tree: Tree, P, tau, K, stream=None):
+    n = tree.nbf
+    _check_matrix(P, n, "P")
+    _check_matrix(K, n, "K")
+    _check(lib().fx_exchange(tree.handle, ctypes.c_void_p(P.data_ptr()), float(tau),
+                             ctypes.c_void_p(K.data_ptr()), _stream_ptr(stream)))
+    return K
+
+
+def fx_exchange_ex(tree: Tree, P, tau, K, opts=None, stream=None):
+    n = tree.nbf
+    _check_matrix(P, n, "P")
+    _check_matrix(K, n, "K")
+    st = fx_stats()
+    o = opts if opts is not None else make_opts()
+    _check(lib().fx_exchange_ex(tree.handle, ctypes.c_void_p(P.data_ptr()), float(tau),
+                                ctypes.c_void_p(K.data_ptr()), ctypes.byref(o), ctypes.byref(st),
+                                _stream_ptr(stream)))
+    return K, st.as_dict()
+
+
+def fx_exchange_batched(trees, Ps, Ks, tau, opts=None, stream=None):
+    count = len(trees)
+    for t, P, K in zip(trees, Ps, Ks):
+        _check_matrix(P, t.nbf, "P")
+        _check_matrix(K, t.nbf, "K")
+    VP = ctypes.c_void_p * count
+    th = VP(*[t.handle for t in trees])
+    ph = VP(*[P.data_ptr() for P in Ps])
+    kh = VP(*[K.data_ptr() for K in Ks])
+    st = fx_stats()
+    o = opts if opts is not None else make_opts()
+    _check(lib().fx_exchange_batched(th, ph, kh, count, float(tau), ctypes.byref(o), ctypes.byref(st),
+                                     _stream_ptr(stream)))
+    return Ks, st.as_dict()
+
+
+def fx_plan_tree(l, nprim, center, exps, coefs, leaf_max_functions=10, ordering=0):
+    """Host-only planning: (perm, nodes[level, first shell, end shell, children])."""
+    sh = _ShellArrays(l, nprim, center, exps, coefs)
+    opts = fx_tree_opts(int(leaf_max_functions), int(ordering))
+    S = len(sh.l)
+    perm = np.zeros(S, np.int32)
+    nlev = ctypes.c_int32()
+    nn = ctypes.c_int64()
+    _check(lib().fx_plan_tree(ctypes.byref(sh.s), ctypes.byref(opts),
+                              perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(nlev), None, 0,
+                              ctypes.byref(nn)))
+    nodes = np.zeros((nn.value, 4), np.int32)
+    _check(lib().fx_plan_tree(ctypes.byref(sh.s), ctypes.byref(opts),
+                              perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(nlev),
+                              nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), nn.value, ctypes.byref(nn)))
+    return perm, nodes
+
+
+def hilbert_key3(x, y, z, bits):
+    return int(lib().fx_hilbert_key3(x, y, z, bits))

@@ -1,0 +1,174 @@
+"""GPU parity: the HIP exchange build (through the C ABI) against the CPU
+oracle, element by element, on seeded synthetic inputs.
+
+Bar: FP64 path within 1e-10 max-abs of the oracle; the computed shell
+quartet set identical (exact integer counts per angular-momentum class).
+The only admissible count difference would come from quartets whose bound
+lies within 1e-10 relative of tau (both sides evaluate the same bound
+expression, the Schwarz factors from different integral algorithms); the
+oracle reports how many such quartets exist, and the tests require none.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+fx = pytest.importorskip("paper_1401_6961_amd")
+
+TOL64 = 1e-10
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def gpu_exchange(sys_, tau, P=None, tree=None, **opts):
+    if tree is None:
+        tree = fx.build_quadtree_from(sys_)
+    Pt = torch.from_numpy(np.ascontiguousarray(sys_.P if P is None else P)).cuda()
+    K = torch.zeros_like(Pt)
+    K, st = fx.fx_exchange_ex(tree, Pt, tau, K, fx.make_opts(**opts))
+    torch.cuda.synchronize()
+    return K.cpu().numpy(), st, tree
+
+
+def spd_cube(natom, edge, seed, tau=1e-11):
+    rng = np.random.default_rng(seed)
+    atoms = synthetic.cube_atoms(rng, natom, edge)
+    return synthetic.assemble(f"spd{natom}", rng, atoms, True, 2.0, tau)
+
+
+@pytest.fixture(scope="module")
+def spd5():
+    return spd_cube(5, 4.0, 31)
+
+
+def test_schwarz_norms(spd5):
+    say("gpu: schwarz spd5")
+    tree = fx.build_quadtree_from(spd5)
+    Qg = tree.schwarz()
+    Qo = oracle.schwarz(spd5)
+    assert np.all(np.abs(Qg - Qo) <= 1e-12 * np.maximum(Qo, 1e-300) + 1e-300)
+
+
+def test_all_classes_fp64(spd5):
+    say("gpu: all 81 classes fp64, spd5 tau=1e-11")
+    Ko, sto = oracle.exchange(spd5, tau=1e-11)
+    cnt, _, near = oracle.count(spd5, tau=1e-11)
+    Kg, st, _ = gpu_exchange(spd5, 1e-11)
+    assert near == 0
+    assert np.array_equal(st["class_quartets"], cnt)
+    assert st["quartets"] == sto["quartets"]
+    assert np.abs(Kg - Ko).max() <= TOL64
+
+
+def test_bruteforce_tau0(spd5):
+    say("gpu: tau=0 vs oracle brute force")
+    Ko, _ = oracle.exchange(spd5, tau=-1.0)
+    Kg, st, _ = gpu_exchange(spd5, 0.0)
+    assert np.abs(Kg - Ko).max() <= TOL64
+
+
+def test_probe_density_slices(spd5):
+    """P = e_nu e_lam^T + e_lam e_nu^T gives K_{mu sig} = (mu nu|lam sig) + (mu lam|nu sig)."""
+    say("gpu: probe densities")
+    n = spd5.nbf
+    T = oracle.eri_tensor(spd5)
+    tree = fx.build_quadtree_from(spd5)
+    for nu, lam in [(0, 0), (3, 17), (20, 44), (9, 9)]:
+        P = np.zeros((n, n))
+        P[nu, lam] += 1.0
+        P[lam, nu] += 1.0
+        Kg, _, _ = gpu_exchange(spd5, 0.0, P=P, tree=tree)
+        ref = T[:, nu, lam, :] + T[:, lam, nu, :]
+        assert np.abs(Kg - ref).max() <= TOL64
+
+
+def test_tiny_cube_config(request):
+    say("gpu: 24-atom s+p cube, tau=1e-12")
+    s = synthetic.config(0)
+    Ko, sto = oracle.exchange(s)
+    Kg, st, _ = gpu_exchange(s, s.tau)
+    assert sto["near_threshold"] == 0
+    assert st["quartets"] == sto["quartets"]
+    assert st["prim_quartets"] == sto["prim_quartets"]
+    assert np.abs(Kg - Ko).max() <= TOL64
+
+
+@pytest.fixture(scope="module")
+def chain():
+    s = synthetic.config(1)
+    Ko, sto = oracle.exchange(s)
+    return s, Ko, sto
+
+
+def test_chain_config(chain):
+    say("gpu: 200-atom chain, tau=1e-8")
+    s, Ko, sto = chain
+    Kg, st, _ = gpu_exchange(s, s.tau)
+    assert sto["near_threshold"] == 0
+    assert st["quartets"] == sto["quartets"]
+    assert np.abs(Kg - Ko).max() <= TOL64
+    assert np.abs(Kg - Kg.T).max() <= 1e-12
+
+
+def test_chunked_traversal_is_bitwise_identical(chain):
+    say("gpu: chunked traversal (frontier cap 2000)")
+    s, _, _ = chain
+    K1, st1, tree = gpu_exchange(s, s.tau)
+    K2, st2, _ = gpu_exchange(s, s.tau, tree=tree, max_frontier_entries=2000)
+    assert st2["chunks"] > 0
+    assert st1["quartets"] == st2["quartets"]
+    assert np.array_equal(K1, K2)
+
+
+def test_rerun_is_bitwise_identical(chain):
+    say("gpu: determinism")
+    s, _, _ = chain
+    K1, _, tree = gpu_exchange(s, s.tau)
+    K2, _, _ = gpu_exchange(s, s.tau, tree=tree)
+    assert np.array_equal(K1, K2)
+
+
+def test_alpha_beta(spd5):
+    say("gpu: alpha/beta")
+    n = spd5.nbf
+    Kg, _, tree = gpu_exchange(spd5, 1e-11)
+    Pt = torch.from_numpy(spd5.P).cuda()
+    K0 = torch.from_numpy(np.full((n, n), 2.0)).cuda()
+    K, _ = fx.fx_exchange_ex(tree, Pt, 1e-11, K0, fx.make_opts(alpha=-0.5, beta=3.0))
+    assert np.abs(K.cpu().numpy() - (-0.5 * Kg + 6.0)).max() <= 1e-12
+
+
+def test_tree_shape_and_order_independence(spd5):
+    """Reading of the leaf rule: the quartet set is {beta_q > tau} whatever
+    the leaf size or shell order, so K agrees to rounding."""
+    say("gpu: leaf size / ordering independence")
+    Kref, st0, _ = gpu_exchange(spd5, 1e-9)
+    for leaf, order in [(1, 0), (4, 0), (30, 0), (10, 1)]:
+        tree = fx.build_quadtree_from(spd5, leaf_max_functions=leaf, ordering=order)
+        K, st, _ = gpu_exchange(spd5, 1e-9, tree=tree)
+        assert st["quartets"] == st0["quartets"]
+        assert np.abs(K - Kref).max() <= 1e-13
+
+
+def test_mixed_precision_tolerance(chain):
+    say("gpu: mixed precision on the chain")
+    s, Ko, _ = chain
+    K64, st64, tree = gpu_exchange(s, s.tau)
+    Km, stm, _ = gpu_exchange(s, s.tau, tree=tree, precision=fx.FX_PREC_MIXED)
+    assert stm["quartets"] == st64["quartets"]
+    assert stm["quartets_fp32"] > 0
+    assert np.abs(Km - Ko).max() <= 1e-7
+
+
+def test_mixed_precision_all_classes(spd5):
+    say("gpu: mixed precision all classes")
+    Ko, _ = oracle.exchange(spd5, tau=1e-11)
+    Km, stm, _ = gpu_exchange(spd5, 1e-11, precision=fx.FX_PREC_MIXED)
+    assert stm["quartets_fp32"] > 0
+    assert np.abs(Km - Ko).max() <= 1e-7
