@@ -105,6 +105,7 @@ typedef struct fx_exchange_opts {
     const fx_costmodel* costmodel;
     double alpha, beta;         /* K <- alpha*K_x + beta*K; default 1, 0     */
     int64_t max_frontier_entries; /* traversal chunking threshold, 0 = auto  */
+    int32_t profile;            /* 1: time every class-kernel launch with HIP events on `stream` */
 } fx_exchange_opts;
 
 /* Statistics of one fx_exchange_ex call (valid when the call returns). */
@@ -120,6 +121,11 @@ typedef struct fx_stats {
     double prim_quartets;                        /* primitive quartets        */
     double flops;                                /* algorithmic flops (generated-code count) */
     int32_t chunks;                              /* traversal chunks          */
+    /* with opts.profile: per class and precision (index cls*2 + fp32) */
+    double class_seconds[162];                   /* summed kernel time (HIP events) */
+    int32_t class_launches[162];                 /* launches                   */
+    double class_flops[162];                     /* algorithmic flops          */
+    int64_t class_prec_quartets[162];            /* computed quartets          */
     double seconds_traversal, seconds_eri, seconds_total; /* host wall clock */
 } fx_stats;
 

@@ -11,7 +11,7 @@
 
 struct FxShellRef {
     double x, y, z;
-    int nprim, pofs;
+    int nprim, pofs, idx;
 };
 
 __device__ __forceinline__ FxShellRef fx_shell(const FxDevBasis& B, int s) {
@@ -21,6 +21,7 @@ __device__ __forceinline__ FxShellRef fx_shell(const FxDevBasis& B, int s) {
     r.z = B.xyz[3 * s + 2];
     r.nprim = B.nprim[s];
     r.pofs = B.pofs[s];
+    r.idx = s;
     return r;
 }
 
@@ -29,17 +30,18 @@ __device__ __forceinline__ FxShellRef fx_shell(const FxDevBasis& B, int s) {
 //   T < FX_BOYS_TMAX: 6th-order Taylor expansion of F_M about the nearest
 //   tabulated point T_i = i/32 (dF_m/dT = -F_{m+1}), then the downward
 //   recursion F_m = (2T F_{m+1} + e^{-T}) / (2m+1).
-//   T >= FX_BOYS_TMAX: F_0 = (1/2) sqrt(pi/T) (erf(sqrt T) = 1 to FP64) and
-//   the upward recursion F_{m+1} = ((2m+1) F_m - e^{-T}) / (2T), stable for
-//   T > m + 1/2.
-// The table (F_j(T_i), j = 0..FX_BOYS_NCOL-1) is built on the host.
+//   T >= FX_BOYS_TMAX (60): F_0 = (1/2) sqrt(pi/T) (erf(sqrt T) = 1 to FP64)
+//   and the upward recursion F_{m+1} = ((2m+1) F_m - e^{-T}) / (2T), in which
+//   e^{-T} is negligible.
+// The table (F_j(T_i) and e^{-T_i}) is built on the host.
 // ---------------------------------------------------------------------------
 template <int M>
 __device__ __forceinline__ void fx_boys(double T, const double* __restrict__ tab, double* F) {
     if (T < FX_BOYS_TMAX) {
         const int i = (int)(T * FX_BOYS_INV_DT + 0.5);
-        const double dt = (double)i * FX_BOYS_DT - T;   // T_i - T
-        const double* r = tab + i * FX_BOYS_NCOL + M;
+        const double dt = (double)i * FX_BOYS_DT - T;   // T_i - T, |dt| <= 1/64
+        const double* row = tab + i * FX_BOYS_NCOL;
+        const double* r = row + M;
         double f = r[6] * (dt * (1.0 / 6.0));
         f = (r[5] + f) * (dt * (1.0 / 5.0));
         f = (r[4] + f) * (dt * (1.0 / 4.0));
@@ -48,18 +50,24 @@ __device__ __forceinline__ void fx_boys(double T, const double* __restrict__ tab
         f = (r[1] + f) * dt;
         F[M] = r[0] + f;
         if (M > 0) {
-            const double eT = exp(-T), T2 = 2.0 * T;
+            // e^{-T} = e^{-T_i} e^{dt}, e^{dt} by its Taylor series to dt^7
+            double x = 1.0 + dt * (1.0 / 7.0);
+            x = 1.0 + dt * (1.0 / 6.0) * x;
+            x = 1.0 + dt * (1.0 / 5.0) * x;
+            x = 1.0 + dt * (1.0 / 4.0) * x;
+            x = 1.0 + dt * (1.0 / 3.0) * x;
+            x = 1.0 + dt * 0.5 * x;
+            x = 1.0 + dt * x;
+            const double eT = row[FX_BOYS_NCOL - 1] * x, T2 = 2.0 * T;
 #pragma unroll
             for (int m = M - 1; m >= 0; --m) F[m] = (T2 * F[m + 1] + eT) * (1.0 / (2 * m + 1));
         }
     } else {
+        // e^{-T} < 1e-26 is below FP64 resolution of every F_m (m <= 8) here
         const double oT = 1.0 / T;
         F[0] = 0.88622692545275801365 * sqrt(oT);   // sqrt(pi)/2 / sqrt(T)
-        if (M > 0) {
-            const double eT = exp(-T), h = 0.5 * oT;
 #pragma unroll
-            for (int m = 0; m < M; ++m) F[m + 1] = ((2 * m + 1) * F[m] - eT) * h;
-        }
+        for (int m = 0; m < M; ++m) F[m + 1] = (2 * m + 1) * F[m] * (0.5 * oT);
     }
 }
 
@@ -123,11 +131,13 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
     constexpr int NA = fx_ncart(LA), ND = fx_ncart(LD);
     __shared__ int2 queue[FX_CLASS_WAVES][128];
     const int lane = fx_lane();
-    const int wave = (int)(threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const long slot_unit = (long)blockIdx.x * FX_CLASS_WAVES + wave;
     if (slot_unit >= A.nunits) return;
-    const int u = A.order ? A.order[slot_unit] : (int)slot_unit;
-    const int item = A.units[3 * u], a = A.units[3 * u + 1], d = A.units[3 * u + 2];
+    const int u = __builtin_amdgcn_readfirstlane(A.order ? A.order[slot_unit] : (int)slot_unit);
+    const int item = __builtin_amdgcn_readfirstlane(A.units[3 * u]);
+    const int a = __builtin_amdgcn_readfirstlane(A.units[3 * u + 1]);
+    const int d = __builtin_amdgcn_readfirstlane(A.units[3 * u + 2]);
     const FxDevBasis& Bs = A.basis;
     const int S = Bs.nshell;
     const FxShellRef ra = fx_shell(Bs, a), rd = fx_shell(Bs, d);
@@ -146,51 +156,83 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
         const FxShellRef rb = fx_shell(Bs, q.x), rc = fx_shell(Bs, q.y);
         npq += (long)(ra.nprim * rb.nprim) * (rc.nprim * rd.nprim);
         const double* Pblk = A.P + (long)Bs.f0[q.x] * A.n + Bs.f0[q.y];
-        fn(ra, rb, rc, rd, Bs.exps, Bs.coefs, A.boys, Pblk, A.n, kacc);
+        fn(ra, rb, rc, rd, Bs, A.boys, Pblk, A.n, kacc);
     };
-    for (long base = e0; base < e1; base += 64) {
-        const long e = base + lane;
-        int nb = 0, nc = 0, ob = 0, oc = 0;
-        if (e < e1) {
-            const int2 bc = A.bc[e];
-            ob = Bs.leaf_lofs[bc.x * 4 + LB];
-            nb = Bs.leaf_lofs[bc.x * 4 + LB + 1] - ob;
-            oc = Bs.leaf_lofs[bc.y * 4 + LC];
-            nc = Bs.leaf_lofs[bc.y * 4 + LC + 1] - oc;
-        }
-        const int ncand = nb * nc;
-        const int maxc = fx_wave_max(ncand);
-        for (int k = 0; k < maxc; ++k) {
-            bool ok = false;
-            int b = 0, c = 0;
-            if (k < ncand) {
-                const int kb = k / nc;
-                b = Bs.leaf_lsh[ob + kb];
-                c = Bs.leaf_lsh[oc + (k - kb * nc)];
-                const double beta = (Qa[b] * Qd[c]) * A.Pn[(long)b * S + c];
-                ok = beta > tau;
-                if (mode == FX_MODE_MIXED_HI) ok = ok && !(beta < thr);
-                else if (mode == FX_MODE_MIXED_LO) ok = ok && (beta < thr);
+    auto test = [&](int b, int c) {
+        const double beta = (Qa[b] * Qd[c]) * A.Pn[(long)b * S + c];
+        bool ok = beta > tau;
+        if (mode == FX_MODE_MIXED_HI) ok = ok && !(beta < thr);
+        else if (mode == FX_MODE_MIXED_LO) ok = ok && (beta < thr);
+        return ok;
+    };
+    auto push = [&](bool ok, int b, int c) {
+        const uint64_t m = __ballot(ok);
+        if (ok) queue[wave][qn + fx_mbcnt(m)] = make_int2(b, c);
+        qn += __popcll(m);
+    };
+    // Candidate cursor: single-shell leaves read the item's (lb, lc) segment
+    // (leaf index == shell index); larger leaves enumerate b in B, c in C.
+    const bool seg = A.cls_off != nullptr;
+    long cur = seg ? A.cls_off[(long)item * 10 + LB * 3 + LC] : e0;
+    const long cend = seg ? A.cls_off[(long)item * 10 + LB * 3 + LC + 1] : e1;
+    int kc = 0, maxc = 0, nb = 0, nc = 0, ob = 0, oc = 0;
+    while (true) {
+        // fill: screen candidates until a full batch is queued or none are left
+        while (qn < 64) {
+            if (seg) {
+                if (cur >= cend) break;
+                const long e = cur + lane;
+                bool ok = false;
+                int b = 0, c = 0;
+                if (e < cend) {
+                    const int2 bc = A.bc[e];
+                    b = bc.x;
+                    c = bc.y;
+                    ok = test(b, c);
+                }
+                push(ok, b, c);
+                cur += 64;
+            } else {
+                if (kc >= maxc) {
+                    if (cur >= cend) break;
+                    const long e = cur + lane;
+                    nb = nc = ob = oc = 0;
+                    if (e < cend) {
+                        const int2 bc = A.bc[e];
+                        ob = Bs.leaf_lofs[bc.x * 4 + LB];
+                        nb = Bs.leaf_lofs[bc.x * 4 + LB + 1] - ob;
+                        oc = Bs.leaf_lofs[bc.y * 4 + LC];
+                        nc = Bs.leaf_lofs[bc.y * 4 + LC + 1] - oc;
+                    }
+                    maxc = fx_wave_max(nb * nc);
+                    kc = 0;
+                    cur += 64;
+                    continue;
+                }
+                bool ok = false;
+                int b = 0, c = 0;
+                if (kc < nb * nc) {
+                    const int kb = kc / nc;
+                    b = Bs.leaf_lsh[ob + kb];
+                    c = Bs.leaf_lsh[oc + (kc - kb * nc)];
+                    ok = test(b, c);
+                }
+                push(ok, b, c);
+                ++kc;
             }
-            const uint64_t m = __ballot(ok);
-            if (ok) queue[wave][qn + fx_mbcnt(m)] = make_int2(b, c);
-            qn += __popcll(m);
-            fx_wave_sync();
-            if (qn >= 64) {
-                const int2 q = queue[wave][lane];
-                const int2 t = queue[wave][lane + 64];
-                evaluate(q);
-                nq += 64;
-                fx_wave_sync();
-                queue[wave][lane] = t;
-                qn -= 64;
-                fx_wave_sync();
-            }
         }
-    }
-    if (qn > 0) {
-        if (lane < qn) evaluate(queue[wave][lane]);
-        nq += qn;
+        fx_wave_sync();
+        if (qn == 0) break;
+        // evaluate one batch (the only call site of the quartet routine)
+        const int nbatch = qn < 64 ? qn : 64;
+        const int2 q = queue[wave][lane];
+        const int2 t = queue[wave][lane + 64];
+        if (lane < nbatch) evaluate(q);
+        nq += nbatch;
+        fx_wave_sync();
+        queue[wave][lane] = t;
+        qn -= nbatch;
+        fx_wave_sync();
     }
     // deterministic reduction of the 64 lane partials, then one write per element
     const long rowbase = (long)Bs.f0[a] * A.n + Bs.f0[d];
@@ -215,15 +257,15 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
 #define FX_DEFINE_CLASS_KERNELS(la, lb, lc, ld, cls)                                                   \
     __global__ __launch_bounds__(64 * FX_CLASS_WAVES) void fx_k_##cls##_f64(FxClassArgs A) {            \
         fx_class_body<la, lb, lc, ld>(A, [](const FxShellRef& ra, const FxShellRef& rb,                 \
-                                            const FxShellRef& rc, const FxShellRef& rd, const double* e,  \
-                                            const double* c, const double* bt, const double* P, long n,   \
-                                            double* k) { eri_##cls##_f64(ra, rb, rc, rd, e, c, bt, P, n, k); }); \
+                                            const FxShellRef& rc, const FxShellRef& rd, const FxDevBasis& B, \
+                                            const double* bt, const double* P, long n,                    \
+                                            double* k) { eri_##cls##_f64(ra, rb, rc, rd, B, bt, P, n, k); }); \
     }                                                                                                   \
     __global__ __launch_bounds__(64 * FX_CLASS_WAVES) void fx_k_##cls##_f32(FxClassArgs A) {            \
         fx_class_body<la, lb, lc, ld>(A, [](const FxShellRef& ra, const FxShellRef& rb,                 \
-                                            const FxShellRef& rc, const FxShellRef& rd, const double* e,  \
-                                            const double* c, const double* bt, const double* P, long n,   \
-                                            double* k) { eri_##cls##_f32(ra, rb, rc, rd, e, c, bt, P, n, k); }); \
+                                            const FxShellRef& rc, const FxShellRef& rd, const FxDevBasis& B, \
+                                            const double* bt, const double* P, long n,                    \
+                                            double* k) { eri_##cls##_f32(ra, rb, rc, rd, B, bt, P, n, k); }); \
     }                                                                                                   \
     void fx_launch_##cls(int prec32, FxClassArgs A, int grid, hipStream_t st) {                         \
         if (prec32) hipLaunchKernelGGL(fx_k_##cls##_f32, dim3(grid), dim3(64 * FX_CLASS_WAVES), 0, st, A); \
@@ -233,7 +275,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
 // Schwarz factors: one thread per unordered shell pair (a <= b) of the pair
 // type (la, lb); Qn[a][b] = Qn[b][a] = sqrt(sum max(0, (mu nu|mu nu))).
 #define FX_SCHWARZ_CASE(la, lb, cls)                                                                    \
-    case (la * 3 + lb): s2 = eri_diag_##cls##_f64(r0, r1, B.exps, B.coefs, boys); break;
+    case (la * 3 + lb): s2 = eri_diag_##cls##_f64(r0, r1, B, boys); break;
 
 #define FX_DEFINE_SCHWARZ_KERNEL()                                                                      \
     __global__ __launch_bounds__(256) void fx_k_schwarz(FxDevBasis B, const double* boys, const int2* pairs, \

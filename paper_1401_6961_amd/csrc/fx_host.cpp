@@ -158,7 +158,7 @@ static std::vector<double> boys_table() {
     for (int i = 0; i < FX_BOYS_NROW; ++i) {
         const long double T = (long double)i * (long double)FX_BOYS_DT;
         const long double eT = expl(-T);
-        for (int j = 0; j < FX_BOYS_NCOL; ++j) {
+        for (int j = 0; j < FX_BOYS_NF; ++j) {
             long double term = 1.0L / (2 * j + 1), sum = term;
             for (int k = 1; k < 4000; ++k) {
                 term *= 2.0L * T / (long double)(2 * j + 2 * k + 1);
@@ -167,6 +167,7 @@ static std::vector<double> boys_table() {
             }
             tab[(size_t)i * FX_BOYS_NCOL + j] = (double)(eT * sum);
         }
+        tab[(size_t)i * FX_BOYS_NCOL + FX_BOYS_NCOL - 1] = (double)eT;
     }
     return tab;
 }
@@ -238,7 +239,7 @@ static void validate_shells(const fx_shells* s) {
 
 static Plan make_plan(const fx_shells* s, const fx_tree_opts* opts) {
     const int S = s->nshell;
-    const int leaf_max = (opts && opts->leaf_max_functions > 0) ? opts->leaf_max_functions : 10;
+    const int leaf_max = (opts && opts->leaf_max_functions > 0) ? opts->leaf_max_functions : 1;
     const int ordering = opts ? opts->ordering : 0;
     if (opts && (opts->ordering < 0 || opts->ordering > 1)) fx_fail(FX_ERR_INVALID_ARG, "ordering must be 0 or 1");
     Plan P;
@@ -316,6 +317,7 @@ struct fx_tree {
     std::vector<int> f0;             // tree order, caller function offset
     std::vector<Level> levels;
     std::vector<int> leaf_lofs;      // host copy
+    bool single_shell_leaves = false;
     hipStream_t build_stream = nullptr;
     DevArena* arena = nullptr;
     FxDevBasis basis{};
@@ -392,6 +394,7 @@ static void build_tree(const fx_shells* s, const fx_tree_opts* opts, hipStream_t
         lofs[A * 4 + 3] = (int)lsh.size();
     }
     T->leaf_lofs = lofs;
+    T->single_shell_leaves = (int)leaf.sL.size() == S;
 
     T->arena = new DevArena(st, true);
     DevArena& A = *T->arena;
@@ -408,6 +411,21 @@ static void build_tree(const fx_shells* s, const fx_tree_opts* opts, hipStream_t
     B.leaf_lofs = upload(A, lofs);
     B.leaf_lsh = upload(A, lsh.empty() ? std::vector<int>{0} : lsh);
     T->boys = upload(A, boys_table());
+    // primitive pairs of every ordered pair of primitives
+    {
+        const long Nt = (long)ex.size();
+        std::vector<int> prim_shell(Nt);
+        for (int t = 0; t < S; ++t)
+            for (int p = 0; p < np[t]; ++p) prim_shell[pofs[t] + p] = t;
+        DevArena tmp(st);
+        int* dps = upload(tmp, prim_shell);
+        FxPrimPair* pp = A.get<FxPrimPair>((size_t)Nt * Nt);
+        fx_launch_prim_pairs(B.exps, B.coefs, dps, B.xyz, Nt, pp, st);
+        FX_HIP(hipGetLastError());
+        FX_HIP(hipStreamSynchronize(st));
+        B.ntprim = Nt;
+        B.pp = pp;
+    }
     for (const Level& L : P.levels) {
         T->d_sL.push_back(upload(A, L.sL));
         T->d_sR.push_back(upload(A, L.sR));
@@ -477,6 +495,12 @@ struct ExCtx {
     long scan_partial_cap;
     long* scan_total;
     double seconds_eri = 0;
+    int profile = 0;
+    struct Timed {
+        int idx;
+        hipEvent_t a, b;
+    };
+    std::vector<Timed> timed;
 };
 
 static int slot_index(const ExCtx& c, int lb, int lc, int prec32) {
@@ -519,6 +543,17 @@ static void leaf_work(ExCtx& c, const Frontier& f) {
     args.Pn = c.Pn;
     args.bc_off = f.bc_off;
     args.bc = f.bc;
+    args.cls_off = nullptr;
+    if (T->single_shell_leaves) {
+        // leaf-level frontiers are always fresh arrays (chunking splits above the leaf level)
+        if (f.e_begin != 0) fx_fail(FX_ERR_INTERNAL, "leaf frontier does not start at entry 0");
+        const long ne = f.e_count;
+        int2* sorted = A.get<int2>(std::max(1L, ne));
+        long* cls_off = A.get<long>(10 * nitems);
+        fx_launch_class_sort(f.bc_off, f.bc, nitems, T->basis.l, sorted, cls_off, st);
+        args.bc = sorted;
+        args.cls_off = cls_off;
+    }
     args.tau = c.tau;
     args.thr = c.thr;
     const int Lm = T->lmax;
@@ -540,7 +575,17 @@ static void leaf_work(ExCtx& c, const Frontier& f) {
                                                                  : FX_MODE_ALL;
                         args.kslot = c.slots + (long)slot_index(c, lb, lc, pr) * T->n * T->n;
                         args.counters = c.counters + (cls * 2 + pr) * 2;
-                        fx_class_table[cls](pr, args, grid, st);
+                        if (c.profile) {
+                            ExCtx::Timed t{cls * 2 + pr, nullptr, nullptr};
+                            FX_HIP(hipEventCreate(&t.a));
+                            FX_HIP(hipEventCreate(&t.b));
+                            FX_HIP(hipEventRecord(t.a, st));
+                            fx_class_table[cls](pr, args, grid, st);
+                            FX_HIP(hipEventRecord(t.b, st));
+                            c.timed.push_back(t);
+                        } else {
+                            fx_class_table[cls](pr, args, grid, st);
+                        }
                     }
                 }
         }
@@ -617,7 +662,8 @@ static void traverse(ExCtx& c, int k, const Frontier& f) {
     g.ad = N.get<int2>(std::max(1L, nads));
     g.bc_off = N.get<long>(nads + 1);
     g.bc = N.get<int2>(std::max(1L, total));
-    g.parent = N.get<int>(std::max(1L, total));
+    const bool last = (k + 1 == nl - 1);   // the leaf level needs no parent links
+    g.parent = last ? nullptr : N.get<int>(std::max(1L, total));
     g.nad = (int)nads;
     g.e_begin = 0;
     g.e_count = total;
@@ -673,6 +719,7 @@ static void exchange_impl(const fx_tree* T, const double* P, double tau, double*
     c.cm = o.costmodel;
     c.cap = o.max_frontier_entries > 0 ? o.max_frontier_entries : (1L << 30);
     c.stats = stats;
+    c.profile = o.profile;
     // density norms
     c.Pn = A.get<double>((size_t)S * S);
     fx_launch_pnorm(P, n, T->basis.l, T->basis.f0, S, c.Pn, st);
@@ -713,6 +760,15 @@ static void exchange_impl(const fx_tree* T, const double* P, double tau, double*
     }
     fx_launch_finalize(c.slots, c.nslot, nn, o.alpha, o.beta, K, st);
     FX_HIP(hipGetLastError());
+    struct EvGuard {
+        ExCtx& c;
+        ~EvGuard() {
+            for (auto& t : c.timed) {
+                (void)hipEventDestroy(t.a);
+                (void)hipEventDestroy(t.b);
+            }
+        }
+    } evguard{c};
     std::vector<unsigned long long> cnt(81 * 4);
     FX_HIP(hipMemcpyAsync(cnt.data(), c.counters, sizeof(unsigned long long) * cnt.size(), hipMemcpyDeviceToHost, st));
     FX_HIP(hipStreamSynchronize(st));
@@ -724,8 +780,17 @@ static void exchange_impl(const fx_tree* T, const double* P, double tau, double*
                 stats->quartets += (int64_t)q;
                 if (pr) stats->quartets_fp32 += (int64_t)q;
                 stats->prim_quartets += (double)pq;
-                stats->flops += (double)pq * fx_class_vrr_flops[cls] + (double)q * fx_class_hrr_flops[cls];
+                const double fl = (double)pq * fx_class_vrr_flops[cls] + (double)q * fx_class_hrr_flops[cls];
+                stats->flops += fl;
+                stats->class_flops[cls * 2 + pr] = fl;
+                stats->class_prec_quartets[cls * 2 + pr] = (int64_t)q;
             }
+        for (auto& t : c.timed) {
+            float ms = 0.f;
+            FX_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+            stats->class_seconds[t.idx] += 1e-3 * ms;
+            stats->class_launches[t.idx] += 1;
+        }
         stats->seconds_eri = c.seconds_eri;
         stats->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         stats->seconds_traversal = stats->seconds_total - c.seconds_eri;

@@ -5,12 +5,21 @@
 
 #define FX_CLASS_WAVES 4          // waves (work units) per class-kernel workgroup
 
-// Boys table: F_j(T_i), T_i = i / 32, i = 0..FX_BOYS_NROW-1, j = 0..FX_BOYS_NCOL-1
+// Boys table: row i holds F_j(T_i), j = 0..14 (highest m 8 + 6 Taylor terms),
+// then e^{-T_i} in column 15; T_i = i / 32, i = 0..FX_BOYS_NROW-1.
 #define FX_BOYS_DT (1.0 / 32.0)
 #define FX_BOYS_INV_DT 32.0
-#define FX_BOYS_TMAX 40.0
-#define FX_BOYS_NCOL 15           // highest m (8) + 6 Taylor terms + 1
-#define FX_BOYS_NROW 1282
+#define FX_BOYS_TMAX 60.0
+#define FX_BOYS_NF 15
+#define FX_BOYS_NCOL 16
+#define FX_BOYS_NROW 1922
+
+// Primitive-pair data, one record per ordered pair of primitives (i of shell
+// x, j of shell y): exponent sum p, 1/p, centre P, and
+// K = c_i c_j exp(-a_i a_j / p |XY|^2) with normalised weights.
+struct FxPrimPair {
+    double p, op, Px, Py, Pz, K;
+};
 
 enum { FX_MODE_ALL = 0, FX_MODE_MIXED_HI = 1, FX_MODE_MIXED_LO = 2 };
 
@@ -27,6 +36,8 @@ struct FxDevBasis {
     const double* Qn;     // [S*S] ||Q_ab||_F
     const int* leaf_lofs; // [nleaf*4] per leaf: offsets of its l=0,1,2 shell lists, then end
     const int* leaf_lsh;  // shell indices grouped per leaf and l
+    long ntprim;          // total primitives Nt
+    const FxPrimPair* pp; // [Nt*Nt] primitive-pair records, (global prim i, global prim j)
 };
 
 // Arguments of one class kernel launch.
@@ -41,6 +52,7 @@ struct FxClassArgs {
     long nunits;
     const long* bc_off;               // per leaf item: offsets into bc
     const int2* bc;                   // (B, C) leaf nodes
+    const long* cls_off;              // single-shell leaves: per item 10 class offsets, else null
     double tau, thr;
     int mode;                         // FX_MODE_*
     double* kslot;                    // n*n slot for this (lb, lc, precision)

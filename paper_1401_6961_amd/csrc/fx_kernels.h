@@ -20,6 +20,9 @@ struct FxLevelArgs {
     double tau2;
 };
 
+struct FxPrimPair;
+void fx_launch_prim_pairs(const double* exps, const double* coefs, const int* prim_shell, const double* xyz, long Nt,
+                          FxPrimPair* out, hipStream_t st);
 void fx_launch_pnorm(const double* P, long n, const int* l, const int* f0, int S, double* Pn, hipStream_t st);
 void fx_launch_leaf_sq(const double* x, int S, const int* sL, const int* sR, int nleaf, double* out, hipStream_t st);
 void fx_launch_level_up(const double* child, int nchild_nodes, const int* ch0, const int* nch, int nk, double* out,
@@ -36,5 +39,7 @@ void fx_launch_expand_write(const FxLevelArgs& L, const uint8_t* mask, const lon
 void fx_launch_unit_count(const int2* items, long nitems, const int* leaf_lofs, int* cnt, hipStream_t st);
 void fx_launch_unit_write(const int2* items, long nitems, long item_base, const int* leaf_lofs, const int* leaf_lsh,
                           const long* upos, int* units, hipStream_t st);
+void fx_launch_class_sort(const long* bc_off, const int2* bc, long nitems, const int* l, int2* out, long* cls_off,
+                          hipStream_t st);
 void fx_launch_fill(double* x, long n, double v, hipStream_t st);
 void fx_launch_finalize(const double* slots, int nslot, long nn, double alpha, double beta, double* K, hipStream_t st);

@@ -42,6 +42,39 @@ void fx_launch_pnorm(const double* P, long n, const int* l, const int* f0, int S
 }
 
 // ---------------------------------------------------------------------------
+// Primitive-pair records for every ordered pair of primitives (global
+// indices i, j): p = a_i + a_j, 1/p, P = (a_i X + a_j Y)/p and
+// K = c_i c_j exp(-a_i a_j / p |X - Y|^2).
+// ---------------------------------------------------------------------------
+__global__ void fx_k_prim_pairs(const double* __restrict__ exps, const double* __restrict__ coefs,
+                                const int* __restrict__ prim_shell, const double* __restrict__ xyz, long Nt,
+                                FxPrimPair* __restrict__ out) {
+    const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long i = blockIdx.y;
+    if (j >= Nt) return;
+    const int x = prim_shell[i], y = prim_shell[j];
+    const double ai = exps[i], aj = exps[j];
+    const double p = ai + aj, op = 1.0 / p;
+    const double X0 = xyz[3 * x], X1 = xyz[3 * x + 1], X2 = xyz[3 * x + 2];
+    const double Y0 = xyz[3 * y], Y1 = xyz[3 * y + 1], Y2 = xyz[3 * y + 2];
+    const double d0 = X0 - Y0, d1 = X1 - Y1, d2 = X2 - Y2;
+    FxPrimPair r;
+    r.p = p;
+    r.op = op;
+    r.Px = (ai * X0 + aj * Y0) * op;
+    r.Py = (ai * X1 + aj * Y1) * op;
+    r.Pz = (ai * X2 + aj * Y2) * op;
+    r.K = coefs[i] * coefs[j] * exp(-ai * aj * op * (d0 * d0 + d1 * d1 + d2 * d2));
+    out[i * Nt + j] = r;
+}
+
+void fx_launch_prim_pairs(const double* exps, const double* coefs, const int* prim_shell, const double* xyz, long Nt,
+                          FxPrimPair* out, hipStream_t st) {
+    dim3 grid((unsigned)((Nt + 255) / 256), (unsigned)Nt);
+    hipLaunchKernelGGL(fx_k_prim_pairs, grid, dim3(256), 0, st, exps, coefs, prim_shell, xyz, Nt, out);
+}
+
+// ---------------------------------------------------------------------------
 // Squared block norms at the leaf level: X[A][B] = sum_{a in A, b in B} x_ab^2
 // (shell ranges of leaf nodes are contiguous in tree order).
 // ---------------------------------------------------------------------------
@@ -294,7 +327,7 @@ __global__ void fx_k_expand_write(FxLevelArgs L, const uint8_t* __restrict__ mas
     for (int jk = 0; jk < 4; ++jk)
         if (m & (1u << jk)) {
             bc_next[o] = make_int2(L.ch0[bc.x] + (jk >> 1), L.ch0[bc.y] + (jk & 1));
-            parent_next[o] = child;
+            if (parent_next) parent_next[o] = child;
             ++o;
         }
 }
@@ -357,6 +390,63 @@ void fx_launch_unit_write(const int2* items, long nitems, long item_base, const 
     if (n > 0)
         hipLaunchKernelGGL(fx_k_unit_write, dim3((n + 255) / 256), dim3(256), 0, st, items, nitems, item_base, leaf_lofs,
                            leaf_lsh, upos, units);
+}
+
+// ---------------------------------------------------------------------------
+// Leaves that are single shells: group every K-block item's (B, C) entries by
+// density-side class (l_b, l_c), stably, one wave per item; cls_off[p*10+k]
+// is the first entry of class k = l_b*3 + l_c, cls_off[p*10+9] the end.
+// ---------------------------------------------------------------------------
+__global__ void fx_k_class_sort(const long* __restrict__ bc_off, const int2* __restrict__ bc, long nitems,
+                                const int* __restrict__ l, int2* __restrict__ out, long* __restrict__ cls_off) {
+    const long p = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (p >= nitems) return;
+    const long e0 = bc_off[p], e1 = bc_off[p + 1];
+    long base[9];
+    for (int c = 0; c < 9; ++c) base[c] = 0;
+    for (long e = e0; e < e1; e += 64) {
+        const long i = e + lane;
+        int k = -1;
+        if (i < e1) {
+            const int2 x = bc[i];
+            k = l[x.x] * 3 + l[x.y];
+        }
+        for (int c = 0; c < 9; ++c) base[c] += __popcll(__ballot(k == c));
+    }
+    long run = e0;
+    for (int c = 0; c < 9; ++c) {
+        const long n = base[c];
+        if (lane == 0) cls_off[p * 10 + c] = run;
+        base[c] = run;
+        run += n;
+    }
+    if (lane == 0) cls_off[p * 10 + 9] = e1;
+    for (long e = e0; e < e1; e += 64) {
+        const long i = e + lane;
+        int k = -1;
+        int2 x = make_int2(0, 0);
+        if (i < e1) {
+            x = bc[i];
+            k = l[x.x] * 3 + l[x.y];
+        }
+        for (int c = 0; c < 9; ++c) {
+            const uint64_t m = __ballot(k == c);
+            if (k == c) {
+                const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                out[base[c] + r] = x;
+            }
+            base[c] += __popcll(m);
+        }
+    }
+}
+
+void fx_launch_class_sort(const long* bc_off, const int2* bc, long nitems, const int* l, int2* out, long* cls_off,
+                          hipStream_t st) {
+    if (nitems > 0)
+        hipLaunchKernelGGL(fx_k_class_sort, dim3((nitems + 3) / 4), dim3(256), 0, st, bc_off, bc, nitems, l, out,
+                           cls_off);
 }
 
 // ---------------------------------------------------------------------------

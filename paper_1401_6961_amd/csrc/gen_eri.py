@@ -276,11 +276,11 @@ def gen_class(la, lb, lc, ld, real, diag=False):
       f"({'abcd'[o[0]]}{'abcd'[o[1]]}|{'abcd'[o[2]]}{'abcd'[o[3]]})")
     if diag:
         w(f"__device__ __forceinline__ double {fname}(const FxShellRef& s0, const FxShellRef& s1,")
-        w(f"    const double* __restrict__ exps, const double* __restrict__ coefs, const double* __restrict__ boys_tab) {{")
+        w(f"    const FxDevBasis& B, const double* __restrict__ boys_tab) {{")
         w("  const FxShellRef& ra = s0; const FxShellRef& rb = s1; const FxShellRef& rc = s0; const FxShellRef& rd = s1;")
     else:
         w(f"__device__ __forceinline__ void {fname}(const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc,")
-        w(f"    const FxShellRef& rd, const double* __restrict__ exps, const double* __restrict__ coefs,")
+        w(f"    const FxShellRef& rd, const FxDevBasis& B,")
         w(f"    const double* __restrict__ boys_tab, const double* __restrict__ Pmat, long ldp, double* __restrict__ kacc) {{")
     roles = ["ra", "rb", "rc", "rd"]
     x = [roles[r] for r in o]
@@ -291,26 +291,21 @@ def gen_class(la, lb, lc, ld, real, diag=False):
     w(f"  for (int k = 0; k < {nacc}; ++k) C[k] = 0;")
     w("  const double ABx = x1.x - x2.x, ABy = x1.y - x2.y, ABz = x1.z - x2.z;")
     w("  const double CDx = x3.x - x4.x, CDy = x3.y - x4.y, CDz = x3.z - x4.z;")
-    w("  const double AB2 = ABx * ABx + ABy * ABy + ABz * ABz;")
-    w("  const double CD2 = CDx * CDx + CDy * CDy + CDz * CDz;")
+    w("  const long Nt = B.ntprim;")
+    w("  const FxPrimPair* __restrict__ pab = B.pp + (long)x1.pofs * Nt + x2.pofs;")
+    w("  const FxPrimPair* __restrict__ pcd = B.pp + (long)x3.pofs * Nt + x4.pofs;")
     w("  for (int i1 = 0; i1 < x1.nprim; ++i1) {")
-    w("    const double a1 = exps[x1.pofs + i1], c1 = coefs[x1.pofs + i1];")
     w("    for (int i2 = 0; i2 < x2.nprim; ++i2) {")
-    w("      const double a2 = exps[x2.pofs + i2];")
-    w("      const double p = a1 + a2, op = 1.0 / p;")
-    w("      const double Kab = c1 * coefs[x2.pofs + i2] * exp(-a1 * a2 * op * AB2);")
-    w("      const double Px = (a1 * x1.x + a2 * x2.x) * op, Py = (a1 * x1.y + a2 * x2.y) * op, Pz = (a1 * x1.z + a2 * x2.z) * op;")
+    w("      const FxPrimPair bra = pab[i1 * Nt + i2];")
+    w("      const double p = bra.p, op = bra.op, Px = bra.Px, Py = bra.Py, Pz = bra.Pz;")
     w("      for (int i3 = 0; i3 < x3.nprim; ++i3) {")
-    w("        const double a3 = exps[x3.pofs + i3], c3 = coefs[x3.pofs + i3];")
     w("        for (int i4 = 0; i4 < x4.nprim; ++i4) {")
-    w("          const double a4 = exps[x4.pofs + i4];")
-    w("          const double q = a3 + a4, oq = 1.0 / q;")
-    w("          const double Kcd = c3 * coefs[x4.pofs + i4] * exp(-a3 * a4 * oq * CD2);")
-    w("          const double Qx = (a3 * x3.x + a4 * x4.x) * oq, Qy = (a3 * x3.y + a4 * x4.y) * oq, Qz = (a3 * x3.z + a4 * x4.z) * oq;")
+    w("          const FxPrimPair ket = pcd[i3 * Nt + i4];")
+    w("          const double q = ket.p, oq = ket.op, Qx = ket.Px, Qy = ket.Py, Qz = ket.Pz;")
     w("          const double ppq = p + q, oppq = 1.0 / ppq, rho = p * q * oppq;")
     w("          const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;")
     w("          const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);")
-    w("          const double pref = FX_TWO_PI_POW_2_5 * op * oq * sqrt(oppq) * Kab * Kcd;")
+    w("          const double pref = FX_TWO_PI_POW_2_5 * op * oq * sqrt(oppq) * bra.K * ket.K;")
     w(f"          double F[{Lsum + 1}];")
     w(f"          fx_boys<{Lsum}>(T, boys_tab, F);")
     for m in range(Lsum + 1):

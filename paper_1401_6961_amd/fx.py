@@ -39,7 +39,7 @@ class fx_exchange_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("fp32_threshold", ctypes.c_double),
                 ("schedule", ctypes.c_int32), ("costmodel", ctypes.c_void_p),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
-                ("max_frontier_entries", ctypes.c_int64)]
+                ("max_frontier_entries", ctypes.c_int64), ("profile", ctypes.c_int32)]
 
 
 class fx_stats(ctypes.Structure):
@@ -48,6 +48,8 @@ class fx_stats(ctypes.Structure):
                 ("quartets", ctypes.c_int64), ("quartets_fp32", ctypes.c_int64),
                 ("class_quartets", ctypes.c_int64 * 81), ("prim_quartets", ctypes.c_double),
                 ("flops", ctypes.c_double), ("chunks", ctypes.c_int32),
+                ("class_seconds", ctypes.c_double * 162), ("class_launches", ctypes.c_int32 * 162),
+                ("class_flops", ctypes.c_double * 162), ("class_prec_quartets", ctypes.c_int64 * 162),
                 ("seconds_traversal", ctypes.c_double), ("seconds_eri", ctypes.c_double),
                 ("seconds_total", ctypes.c_double)]
 
@@ -58,7 +60,11 @@ class fx_stats(ctypes.Structure):
                 "class_quartets": np.array(self.class_quartets, dtype=np.int64).reshape(3, 3, 3, 3),
                 "prim_quartets": self.prim_quartets, "flops": self.flops, "chunks": self.chunks,
                 "seconds_traversal": self.seconds_traversal, "seconds_eri": self.seconds_eri,
-                "seconds_total": self.seconds_total}
+                "seconds_total": self.seconds_total,
+                "class_seconds": np.array(self.class_seconds).reshape(81, 2),
+                "class_launches": np.array(self.class_launches).reshape(81, 2),
+                "class_flops": np.array(self.class_flops).reshape(81, 2),
+                "class_prec_quartets": np.array(self.class_prec_quartets, dtype=np.int64).reshape(81, 2)}
 
 
 EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_batched", "fx_nbf", "fx_nshell",
@@ -192,7 +198,7 @@ class Tree:
             pass
 
 
-def fx_build_quadtree(l, nprim, center, exps, coefs, leaf_max_functions=10, ordering=0, stream=None) -> Tree:
+def fx_build_quadtree(l, nprim, center, exps, coefs, leaf_max_functions=0, ordering=0, stream=None) -> Tree:
     sh = _ShellArrays(l, nprim, center, exps, coefs)
     opts = fx_tree_opts(int(leaf_max_functions), int(ordering))
     h = ctypes.c_void_p()
@@ -206,10 +212,10 @@ def build_quadtree_from(system, **kw) -> Tree:
 
 
 def make_opts(precision=FX_PREC_FP64, fp32_threshold=1e-5, schedule=FX_SCHED_BOUND, costmodel=None, alpha=1.0,
-              beta=0.0, max_frontier_entries=0):
+              beta=0.0, max_frontier_entries=0, profile=False):
     return fx_exchange_opts(int(precision), float(fp32_threshold), int(schedule),
                             ctypes.c_void_p(costmodel.handle if costmodel is not None else None),
-                            float(alpha), float(beta), int(max_frontier_entries))
+                            float(alpha), float(beta), int(max_frontier_entries), int(bool(profile)))
 
 
 def fx_exchange(tree: Tree, P, tau, K, stream=None):
@@ -249,7 +255,7 @@ def fx_exchange_batched(trees, Ps, Ks, tau, opts=None, stream=None):
     return Ks, st.as_dict()
 
 
-def fx_plan_tree(l, nprim, center, exps, coefs, leaf_max_functions=10, ordering=0):
+def fx_plan_tree(l, nprim, center, exps, coefs, leaf_max_functions=0, ordering=0):
     """Host-only planning: (perm, nodes[level, first shell, end shell, children])."""
     sh = _ShellArrays(l, nprim, center, exps, coefs)
     opts = fx_tree_opts(int(leaf_max_functions), int(ordering))
