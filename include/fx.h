@@ -70,8 +70,11 @@ typedef struct fx_shells {
 
 /* Tree options (NULL = defaults).
  *   leaf_max_functions: the ragged bisection of Eq. (1) stops at blocks of
- *     at most this many functions (or a single shell); default 10, as in the
- *     paper's implementation (Section V: blocks of 10x10 or smaller).
+ *     at most this many functions (or a single shell); 0 = default 10, as in
+ *     the paper's implementation (Section V: blocks of 10x10 or smaller).
+ *     Inside a surviving leaf task the class kernels apply the same Eq. (8)
+ *     test to every shell quartet, so K does not depend on this size; 1
+ *     continues the traversal itself down to single shells.
  *   ordering: 0 = Hilbert curve on shell centres (Section III, default),
  *             1 = caller order. */
 typedef struct fx_tree_opts {
@@ -166,6 +169,15 @@ int32_t fx_tree_levels(const fx_tree* tree, int64_t* nodes_per_level);
 /* Copy the shell-pair Schwarz norms ||Q_ab||_F (caller shell order, nshell^2, host). */
 fx_status fx_tree_schwarz(const fx_tree* tree, double* Qn_host);
 void fx_tree_free(fx_tree* tree);
+
+/* Kernel variant of a class (cls = ((la*3+lb)*3+lc)*3+ld) and precision
+ * (prec32 0/1): 0 = one quartet per lane, 1 = one quartet per wave with the
+ * HGP intermediates in LDS.  Chosen by the autotuner; both give the same
+ * quartet set and agree to rounding.  Process-wide setting. */
+fx_status fx_set_class_variant(int32_t cls, int32_t prec32, int32_t variant);
+int32_t fx_get_class_variant(int32_t cls, int32_t prec32);
+/* Bit mask of the variants built for a class (bit 0 thread, bit 1 wave). */
+int32_t fx_class_variants_available(int32_t cls);
 
 /* Device allocator used for all library memory (NULL, NULL restores
  * hipMallocAsync / hipFreeAsync).  Not thread-safe against running calls. */

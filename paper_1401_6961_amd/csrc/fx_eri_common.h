@@ -105,6 +105,16 @@ __device__ __forceinline__ int fx_mbcnt(uint64_t m) {
 
 constexpr int fx_ncart(int l) { return (l + 1) * (l + 2) / 2; }
 
+// 8 x uint16 VRR descriptor: dst, a0, a1, b0 | b1, c1, k, e
+__device__ __forceinline__ uint4 fx_unpack_lo(const uint16_t* p) {
+    const ushort4 v = *(const ushort4*)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint4 fx_unpack_hi(const uint16_t* p) {
+    const ushort4 v = *(const ushort4*)(p + 4);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // Per-component normalisation factors sqrt((2l-1)!!/((2i-1)!!(2j-1)!!(2k-1)!!)),
 // lexicographic Cartesian order; only d has factors other than 1.
 __device__ __forceinline__ double fx_comp_factor(int l, int k) {
@@ -126,13 +136,14 @@ __device__ __forceinline__ double fx_comp_factor(int l, int k) {
 // of the unit, whatever order units are scheduled in.  The block is written
 // once to this class's (lb, lc, precision) slot: no atomics.
 // ---------------------------------------------------------------------------
-template <int LA, int LB, int LC, int LD, typename Fn>
+template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, typename Fn>
 __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
     constexpr int NA = fx_ncart(LA), ND = fx_ncart(LD);
-    __shared__ int2 queue[FX_CLASS_WAVES][128];
+    constexpr int NK = COOP ? 1 : NA * ND;   // K elements held per lane
+    __shared__ int2 queue[WAVES][128];
     const int lane = fx_lane();
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const long slot_unit = (long)blockIdx.x * FX_CLASS_WAVES + wave;
+    const long slot_unit = (long)blockIdx.x * WAVES + wave;
     if (slot_unit >= A.nunits) return;
     const int u = __builtin_amdgcn_readfirstlane(A.order ? A.order[slot_unit] : (int)slot_unit);
     const int item = __builtin_amdgcn_readfirstlane(A.units[3 * u]);
@@ -145,18 +156,18 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
     const double* __restrict__ Qd = Bs.Qn + (long)d * S;
     const double tau = A.tau, thr = A.thr;
     const int mode = A.mode;
-    double kacc[NA * ND];
+    double kacc[NK];
 #pragma unroll
-    for (int i = 0; i < NA * ND; ++i) kacc[i] = 0.0;
+    for (int i = 0; i < NK; ++i) kacc[i] = 0.0;
 
     const long e0 = A.bc_off[item], e1 = A.bc_off[item + 1];
     int qn = 0;
     long nq = 0, npq = 0;
     auto evaluate = [&](int2 q) {
         const FxShellRef rb = fx_shell(Bs, q.x), rc = fx_shell(Bs, q.y);
-        npq += (long)(ra.nprim * rb.nprim) * (rc.nprim * rd.nprim);
+        if (!COOP || lane == 0) npq += (long)(ra.nprim * rb.nprim) * (rc.nprim * rd.nprim);
         const double* Pblk = A.P + (long)Bs.f0[q.x] * A.n + Bs.f0[q.y];
-        fn(ra, rb, rc, rd, Bs, A.boys, Pblk, A.n, kacc);
+        fn(ra, rb, rc, rd, Bs, A.boys, Pblk, A.n, kacc, wave);
     };
     auto test = [&](int b, int c) {
         const double beta = (Qa[b] * Qd[c]) * A.Pn[(long)b * S + c];
@@ -225,9 +236,14 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
         if (qn == 0) break;
         // evaluate one batch (the only call site of the quartet routine)
         const int nbatch = qn < 64 ? qn : 64;
-        const int2 q = queue[wave][lane];
         const int2 t = queue[wave][lane + 64];
-        if (lane < nbatch) evaluate(q);
+        if (COOP) {
+            // the whole wave evaluates the queued quartets one after another
+            for (int i = 0; i < nbatch; ++i) evaluate(queue[wave][i]);
+        } else {
+            const int2 q = queue[wave][lane];
+            if (lane < nbatch) evaluate(q);
+        }
         nq += nbatch;
         fx_wave_sync();
         queue[wave][lane] = t;
@@ -237,10 +253,15 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
     // deterministic reduction of the 64 lane partials, then one write per element
     const long rowbase = (long)Bs.f0[a] * A.n + Bs.f0[d];
     double outv = 0.0;
+    if (COOP) {
+        // lane t already owns element t of the block
+        outv = kacc[0] * (fx_comp_factor(LA, lane / ND) * fx_comp_factor(LD, lane % ND));
+    } else {
 #pragma unroll
-    for (int i = 0; i < NA * ND; ++i) {
-        const double s = fx_wave_sum(kacc[i]);
-        if (lane == i) outv = s * (fx_comp_factor(LA, i / ND) * fx_comp_factor(LD, i % ND));
+        for (int i = 0; i < NK; ++i) {
+            const double s = fx_wave_sum(kacc[i]);
+            if (lane == i) outv = s * (fx_comp_factor(LA, i / ND) * fx_comp_factor(LD, i % ND));
+        }
     }
     if (lane < NA * ND) A.kslot[rowbase + (long)(lane / ND) * A.n + (lane % ND)] = outv;
     if (A.counters) {
@@ -254,22 +275,64 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
     }
 }
 
-#define FX_DEFINE_CLASS_KERNELS(la, lb, lc, ld, cls)                                                   \
-    __global__ __launch_bounds__(64 * FX_CLASS_WAVES) void fx_k_##cls##_f64(FxClassArgs A) {            \
-        fx_class_body<la, lb, lc, ld>(A, [](const FxShellRef& ra, const FxShellRef& rb,                 \
-                                            const FxShellRef& rc, const FxShellRef& rd, const FxDevBasis& B, \
-                                            const double* bt, const double* P, long n,                    \
-                                            double* k) { eri_##cls##_f64(ra, rb, rc, rd, B, bt, P, n, k); }); \
-    }                                                                                                   \
-    __global__ __launch_bounds__(64 * FX_CLASS_WAVES) void fx_k_##cls##_f32(FxClassArgs A) {            \
-        fx_class_body<la, lb, lc, ld>(A, [](const FxShellRef& ra, const FxShellRef& rb,                 \
-                                            const FxShellRef& rc, const FxShellRef& rd, const FxDevBasis& B, \
-                                            const double* bt, const double* P, long n,                    \
-                                            double* k) { eri_##cls##_f32(ra, rb, rc, rd, B, bt, P, n, k); }); \
-    }                                                                                                   \
-    void fx_launch_##cls(int prec32, FxClassArgs A, int grid, hipStream_t st) {                         \
-        if (prec32) hipLaunchKernelGGL(fx_k_##cls##_f32, dim3(grid), dim3(64 * FX_CLASS_WAVES), 0, st, A); \
-        else hipLaunchKernelGGL(fx_k_##cls##_f64, dim3(grid), dim3(64 * FX_CLASS_WAVES), 0, st, A);     \
+// Thread variant: one quartet per lane.
+#define FX_THREAD_KERNEL(la, lb, lc, ld, cls, prec)                                                     \
+    __global__ __launch_bounds__(64 * FX_CLASS_WAVES) void fx_k_##cls##_##prec(FxClassArgs A) {        \
+        fx_class_body<la, lb, lc, ld, false, FX_CLASS_WAVES>(                                           \
+            A, [](const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc, const FxShellRef& rd, \
+                  const FxDevBasis& B, const double* bt, const double* P, long n, double* k, int) {       \
+                eri_##cls##_##prec(ra, rb, rc, rd, B, bt, P, n, k);                                      \
+            });                                                                                          \
+    }
+
+// Cooperative variant: one quartet per wave, intermediates in LDS.
+#define FX_COOP_KERNEL(la, lb, lc, ld, cls, prec, real)                                                 \
+    __global__ __launch_bounds__(64 * FX_COOP_WAVES) void fx_kc_##cls##_##prec(FxClassArgs A) {        \
+        __shared__ real lds[FX_COOP_WAVES * coop_##cls##_##prec::NSLOT];                                 \
+        fx_class_body<la, lb, lc, ld, true, FX_COOP_WAVES>(                                             \
+            A, [&](const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc, const FxShellRef& rd, \
+                   const FxDevBasis& B, const double* bt, const double* P, long n, double* k, int w) {    \
+                eri_##cls##_##prec##_coop(ra, rb, rc, rd, B, bt, P, n,                                   \
+                                          lds + w * coop_##cls##_##prec::NSLOT, k[0]);                   \
+            });                                                                                          \
+    }
+
+#define FX_LAUNCH_THREAD(cls, prec)                                                                     \
+    hipLaunchKernelGGL(fx_k_##cls##_##prec, dim3((A.nunits + FX_CLASS_WAVES - 1) / FX_CLASS_WAVES),      \
+                       dim3(64 * FX_CLASS_WAVES), 0, st, A)
+#define FX_LAUNCH_COOP(cls, prec)                                                                       \
+    hipLaunchKernelGGL(fx_kc_##cls##_##prec, dim3((A.nunits + FX_COOP_WAVES - 1) / FX_COOP_WAVES),      \
+                       dim3(64 * FX_COOP_WAVES), 0, st, A)
+
+// Both variants; `variant` 0 = thread, 1 = cooperative.
+#define FX_DEFINE_CLASS_KERNELS_BOTH(la, lb, lc, ld, cls)                                               \
+    FX_THREAD_KERNEL(la, lb, lc, ld, cls, f64)                                                          \
+    FX_THREAD_KERNEL(la, lb, lc, ld, cls, f32)                                                          \
+    FX_COOP_KERNEL(la, lb, lc, ld, cls, f64, double)                                                    \
+    FX_COOP_KERNEL(la, lb, lc, ld, cls, f32, float)                                                     \
+    int fx_launch_##cls(int prec32, int variant, FxClassArgs A, hipStream_t st) {                        \
+        if (variant == 1) {                                                                              \
+            if (prec32) FX_LAUNCH_COOP(cls, f32); else FX_LAUNCH_COOP(cls, f64);                         \
+            return 1;                                                                                    \
+        }                                                                                                \
+        if (prec32) FX_LAUNCH_THREAD(cls, f32); else FX_LAUNCH_THREAD(cls, f64);                         \
+        return 0;                                                                                        \
+    }
+
+#define FX_DEFINE_CLASS_KERNELS_THREAD(la, lb, lc, ld, cls)                                             \
+    FX_THREAD_KERNEL(la, lb, lc, ld, cls, f64)                                                          \
+    FX_THREAD_KERNEL(la, lb, lc, ld, cls, f32)                                                          \
+    int fx_launch_##cls(int prec32, int, FxClassArgs A, hipStream_t st) {                                \
+        if (prec32) FX_LAUNCH_THREAD(cls, f32); else FX_LAUNCH_THREAD(cls, f64);                         \
+        return 0;                                                                                        \
+    }
+
+#define FX_DEFINE_CLASS_KERNELS_COOP(la, lb, lc, ld, cls)                                               \
+    FX_COOP_KERNEL(la, lb, lc, ld, cls, f64, double)                                                    \
+    FX_COOP_KERNEL(la, lb, lc, ld, cls, f32, float)                                                     \
+    int fx_launch_##cls(int prec32, int, FxClassArgs A, hipStream_t st) {                                \
+        if (prec32) FX_LAUNCH_COOP(cls, f32); else FX_LAUNCH_COOP(cls, f64);                             \
+        return 1;                                                                                        \
     }
 
 // Schwarz factors: one thread per unordered shell pair (a <= b) of the pair

@@ -239,7 +239,7 @@ static void validate_shells(const fx_shells* s) {
 
 static Plan make_plan(const fx_shells* s, const fx_tree_opts* opts) {
     const int S = s->nshell;
-    const int leaf_max = (opts && opts->leaf_max_functions > 0) ? opts->leaf_max_functions : 1;
+    const int leaf_max = (opts && opts->leaf_max_functions > 0) ? opts->leaf_max_functions : 10;
     const int ordering = opts ? opts->ordering : 0;
     if (opts && (opts->ordering < 0 || opts->ordering > 1)) fx_fail(FX_ERR_INVALID_ARG, "ordering must be 0 or 1");
     Plan P;
@@ -463,6 +463,17 @@ static void build_tree(const fx_shells* s, const fx_tree_opts* opts, hipStream_t
 }
 
 // ---------------------------------------------------------------------------
+// kernel variant per class and precision (0 thread-per-quartet, 1 wave-per-
+// quartet); the thread form is the default, the autotuner may switch
+// ---------------------------------------------------------------------------
+static int g_variant[81][2];
+static bool g_variant_init = [] {
+    for (int c = 0; c < 81; ++c)
+        for (int p = 0; p < 2; ++p) g_variant[c][p] = (fx_class_variants[c] & 1) ? 0 : 1;
+    return true;
+}();
+
+// ---------------------------------------------------------------------------
 // exchange
 // ---------------------------------------------------------------------------
 struct Frontier {
@@ -565,7 +576,6 @@ static void leaf_work(ExCtx& c, const Frontier& f) {
             args.units = units + 3 * u0;
             args.nunits = u1 - u0;
             args.order = nullptr;
-            const int grid = (int)((args.nunits + FX_CLASS_WAVES - 1) / FX_CLASS_WAVES);
             for (int lb = 0; lb <= Lm; ++lb)
                 for (int lc = 0; lc <= Lm; ++lc) {
                     const int cls = ((la * 3 + lb) * 3 + lc) * 3 + ld;
@@ -580,11 +590,11 @@ static void leaf_work(ExCtx& c, const Frontier& f) {
                             FX_HIP(hipEventCreate(&t.a));
                             FX_HIP(hipEventCreate(&t.b));
                             FX_HIP(hipEventRecord(t.a, st));
-                            fx_class_table[cls](pr, args, grid, st);
+                            fx_class_table[cls](pr, g_variant[cls][pr], args, st);
                             FX_HIP(hipEventRecord(t.b, st));
                             c.timed.push_back(t);
                         } else {
-                            fx_class_table[cls](pr, args, grid, st);
+                            fx_class_table[cls](pr, g_variant[cls][pr], args, st);
                         }
                     }
                 }
@@ -906,6 +916,25 @@ const char* fx_status_string(fx_status s) {
 }
 
 const char* fx_last_error_message(void) { return g_last_error.c_str(); }
+
+fx_status fx_set_class_variant(int32_t cls, int32_t prec32, int32_t variant) {
+    return fx_guard([&] {
+        if (cls < 0 || cls >= 81 || prec32 < 0 || prec32 > 1 || variant < 0 || variant > 1)
+            fx_fail(FX_ERR_INVALID_ARG, "class 0..80, prec32 0..1, variant 0..1");
+        if (!(fx_class_variants[cls] & (1 << variant))) fx_fail(FX_ERR_UNSUPPORTED, "variant not built for this class");
+        g_variant[cls][prec32] = variant;
+    });
+}
+
+int32_t fx_get_class_variant(int32_t cls, int32_t prec32) {
+    if (cls < 0 || cls >= 81 || prec32 < 0 || prec32 > 1) return -1;
+    return g_variant[cls][prec32];
+}
+
+int32_t fx_class_variants_available(int32_t cls) {
+    if (cls < 0 || cls >= 81) return 0;
+    return fx_class_variants[cls];
+}
 
 // Host-only planning (no device work): the tree order and the bisection
 // levels.  perm[nshell]; nodes: 4 ints per node (level, first shell, end

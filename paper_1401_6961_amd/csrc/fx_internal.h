@@ -3,7 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define FX_CLASS_WAVES 4          // waves (work units) per class-kernel workgroup
+#define FX_CLASS_WAVES 4          // waves (work units) per thread-variant workgroup
+#define FX_COOP_WAVES 2           // waves per cooperative-variant workgroup
 
 // Boys table: row i holds F_j(T_i), j = 0..14 (highest m 8 + 6 Taylor terms),
 // then e^{-T_i} in column 15; T_i = i / 32, i = 0..FX_BOYS_NROW-1.
@@ -60,7 +61,8 @@ struct FxClassArgs {
 };
 
 // Launchers defined in the generated class files.
-#define FX_DECLARE_LAUNCH(cls) void fx_launch_##cls(int prec32, FxClassArgs A, int grid, hipStream_t st);
-typedef void (*fx_class_launcher)(int, FxClassArgs, int, hipStream_t);
+// returns the variant launched (0 thread, 1 cooperative)
+#define FX_DECLARE_LAUNCH(cls) int fx_launch_##cls(int prec32, int variant, FxClassArgs A, hipStream_t st);
+typedef int (*fx_class_launcher)(int, int, FxClassArgs, hipStream_t);
 void fx_launch_schwarz(FxDevBasis B, const double* boys, const int2* pairs, long npairs, double* Qn,
                        hipStream_t st);

@@ -380,20 +380,44 @@ def classes():
     return list(itertools.product(range(3), repeat=4))
 
 
+def pair_size(l1, l2):
+    """Number of accumulated [e0| components of a pair (higher l first)."""
+    hi, lo = max(l1, l2), min(l1, l2)
+    return sum(len(cart(x)) for x in range(hi, hi + lo + 1))
+
+
+# Variants generated per class, by the size of the accumulated [e0|f0] block:
+# one thread per quartet while it fits in registers, the cooperative
+# one-quartet-per-wave form beyond; in between both exist and the autotuner
+# (or the default table) chooses.
+COOP_MIN, THREAD_MAX = 100, 1 << 30
+
+
+def variants(la, lb, lc, ld):
+    nacc = pair_size(la, lb) * pair_size(lc, ld)
+    return (nacc < THREAD_MAX, nacc >= COOP_MIN)
+
+
 def main(outdir):
+    import gen_coop
     os.makedirs(outdir, exist_ok=True)
     stats = []
     for (la, lb, lc, ld) in classes():
         cls = f"{LNAME[la]}{LNAME[lb]}{LNAME[lc]}{LNAME[ld]}"
+        th, co = variants(la, lb, lc, ld)
         parts = []
         for real in ("double", "float"):
             code, fp, fc = gen_class(la, lb, lc, ld, real)
-            parts.append(code)
+            if th:
+                parts.append(code)
             if real == "double":
                 stats.append((cls, fp, fc))
+            if co:
+                parts.append(gen_coop.gen_coop(la, lb, lc, ld, real)[0])
         src = ["// Generated by gen_eri.py -- do not edit.", '#include "fx_eri_common.h"', ""]
         src += parts
-        src.append(f'FX_DEFINE_CLASS_KERNELS({la}, {lb}, {lc}, {ld}, {cls})')
+        kind = "BOTH" if (th and co) else ("THREAD" if th else "COOP")
+        src.append(f'FX_DEFINE_CLASS_KERNELS_{kind}({la}, {lb}, {lc}, {ld}, {cls})')
         path = os.path.join(outdir, f"eri_{cls}.hip")
         new = "\n".join(src) + "\n"
         if not os.path.exists(path) or open(path).read() != new:
@@ -415,6 +439,12 @@ def main(outdir):
     lines += [f"FX_DECLARE_LAUNCH({n})" for n in names]
     lines.append("// indexed by ((la*3+lb)*3+lc)*3+ld")
     lines.append("static const fx_class_launcher fx_class_table[81] = {" + ", ".join(f"fx_launch_{n}" for n in names) + "};")
+    # available variants (bit 0 thread, bit 1 cooperative) and the default choice
+    av = []
+    for (a, b, c, d) in classes():
+        th, co = variants(a, b, c, d)
+        av.append(str((1 if th else 0) | (2 if co else 0)))
+    lines.append("static const int fx_class_variants[81] = {" + ", ".join(av) + "};")
     path = os.path.join(outdir, "eri_table.h")
     new = "\n".join(lines) + "\n"
     if not os.path.exists(path) or open(path).read() != new:

@@ -69,7 +69,8 @@ class fx_stats(ctypes.Structure):
 
 EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_batched", "fx_nbf", "fx_nshell",
             "fx_tree_perm", "fx_tree_levels", "fx_tree_schwarz", "fx_tree_free", "fx_set_allocator",
-            "fx_status_string", "fx_last_error_message", "fx_plan_tree", "fx_hilbert_key3"]
+            "fx_status_string", "fx_last_error_message", "fx_plan_tree", "fx_hilbert_key3",
+            "fx_set_class_variant", "fx_get_class_variant", "fx_class_variants_available"]
 
 
 def lib():
@@ -107,6 +108,12 @@ def lib():
                                ctypes.POINTER(i32), ctypes.POINTER(i32), i64, ctypes.POINTER(i64)]
     L.fx_hilbert_key3.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, i32]
     L.fx_hilbert_key3.restype = ctypes.c_uint64
+    L.fx_set_class_variant.argtypes = [i32, i32, i32]
+    L.fx_set_class_variant.restype = ctypes.c_int
+    L.fx_get_class_variant.argtypes = [i32, i32]
+    L.fx_get_class_variant.restype = i32
+    L.fx_class_variants_available.argtypes = [i32]
+    L.fx_class_variants_available.restype = i32
     _lib = L
     return L
 
@@ -275,3 +282,15 @@ def fx_plan_tree(l, nprim, center, exps, coefs, leaf_max_functions=0, ordering=0
 
 def hilbert_key3(x, y, z, bits):
     return int(lib().fx_hilbert_key3(x, y, z, bits))
+
+
+def fx_set_class_variant(cls, prec32, variant):
+    _check(lib().fx_set_class_variant(int(cls), int(prec32), int(variant)))
+
+
+def fx_get_class_variant(cls, prec32):
+    return int(lib().fx_get_class_variant(int(cls), int(prec32)))
+
+
+def fx_class_variants_available(cls):
+    return int(lib().fx_class_variants_available(int(cls)))

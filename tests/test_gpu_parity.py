@@ -172,3 +172,26 @@ def test_mixed_precision_all_classes(spd5):
     Km, stm, _ = gpu_exchange(spd5, 1e-11, precision=fx.FX_PREC_MIXED)
     assert stm["quartets_fp32"] > 0
     assert np.abs(Km - Ko).max() <= 1e-7
+
+
+def test_cooperative_variants(spd5):
+    """The one-quartet-per-wave kernels agree with the oracle like the
+    one-quartet-per-lane kernels (both precisions)."""
+    say("gpu: cooperative variants, all classes that have them")
+    saved = {}
+    try:
+        for cls in range(81):
+            if fx.fx_class_variants_available(cls) & 2:
+                for p in (0, 1):
+                    saved[(cls, p)] = fx.fx_get_class_variant(cls, p)
+                    fx.fx_set_class_variant(cls, p, 1)
+        assert len(saved) > 0
+        Ko, sto = oracle.exchange(spd5, tau=1e-11)
+        Kg, st, _ = gpu_exchange(spd5, 1e-11)
+        assert st["quartets"] == sto["quartets"]
+        assert np.abs(Kg - Ko).max() <= TOL64
+        Km, _, _ = gpu_exchange(spd5, 1e-11, precision=fx.FX_PREC_MIXED)
+        assert np.abs(Km - Ko).max() <= 1e-7
+    finally:
+        for (cls, p), v in saved.items():
+            fx.fx_set_class_variant(cls, p, v)
