@@ -170,6 +170,53 @@ int32_t fx_tree_levels(const fx_tree* tree, int64_t* nodes_per_level);
 fx_status fx_tree_schwarz(const fx_tree* tree, double* Qn_host);
 void fx_tree_free(fx_tree* tree);
 
+/* ---------------------------------------------------------------------------
+ * Learned scheduling.  A small MLP (4 -> 64 -> 64 -> 1, FP32, ReLU) predicts
+ * the wall time (log2 ns) of one K-block work unit in one class launch from
+ * four features: log2 of the class's flops per quartet, log2(nprim_a nprim_d),
+ * log10 of the unit's Schwarz row bound, log2(1 + candidate entries).  With
+ * FX_SCHED_MLP each class launch dispatches its units heaviest-predicted
+ * first (stable 32-bin ordering); FX_SCHED_BOUND uses the bound-only estimate
+ * log2(flops * nprim_a nprim_d * entries).  Culling is never affected, and K
+ * is bitwise identical under every schedule.
+ * ------------------------------------------------------------------------- */
+typedef struct fx_task_timings fx_task_timings;   /* (features, log2 ns) samples */
+
+typedef struct fx_train_opts {
+    int32_t steps;   /* Adam steps (default 2000)                 */
+    int32_t batch;   /* minibatch size (default 8192)             */
+    float lr;        /* learning rate (default 3e-3)              */
+    uint64_t seed;   /* initialisation and minibatch seed          */
+} fx_train_opts;
+
+/* Run one exchange with per-unit timing probes (wall clock of every unit in
+ * every class launch) and collect (features, log2 ns) samples; K is computed
+ * into library-owned scratch and discarded. */
+fx_status fx_record_task_timings(const fx_tree* tree, const double* P, double tau, const fx_exchange_opts* opts,
+                                 fx_task_timings** out, void* stream);
+/* Samples from host arrays (feats: 4 per sample; cls may be NULL). */
+fx_status fx_task_timings_create(const float* feats, const float* log2_ns, const int32_t* cls, int64_t n,
+                                 fx_task_timings** out);
+int64_t fx_task_timings_count(const fx_task_timings* t);
+fx_status fx_task_timings_get(const fx_task_timings* t, float* feats, float* log2_ns, int32_t* cls);
+void fx_task_timings_free(fx_task_timings* t);
+
+/* Train on the GPU (hand-written forward, backward and Adam kernels). */
+fx_status fx_costmodel_train(const fx_task_timings* data, const fx_train_opts* opts, fx_costmodel** out,
+                             float* final_loss, void* stream);
+/* Parameters: FX_MLP layout of fx_costmodel_nparams() floats (W1[64][4],
+ * b1[64], W2[64][64], b2[64], w3[64], b3); norm[10] = input means, input
+ * standard deviations, target mean, target standard deviation. */
+int32_t fx_costmodel_nparams(void);
+fx_status fx_costmodel_create(const float* params, const float* norm, fx_costmodel** out);
+fx_status fx_costmodel_params(const fx_costmodel* m, float* params, float* norm);
+/* Predicted log2 ns for host feature arrays (4 per sample). */
+fx_status fx_costmodel_predict(const fx_costmodel* m, const float* feats, int64_t n, float* out, void* stream);
+/* Mean squared error on standardised targets and its gradient (host arrays). */
+fx_status fx_costmodel_loss_grad(const fx_costmodel* m, const float* feats, const float* log2_ns, int64_t n,
+                                 float* loss, float* grad, void* stream);
+void fx_costmodel_free(fx_costmodel* m);
+
 /* Kernel variant of a class (cls = ((la*3+lb)*3+lc)*3+ld) and precision
  * (prec32 0/1): 0 = one quartet per lane, 1 = one quartet per wave with the
  * HGP intermediates in LDS.  Chosen by the autotuner; both give the same

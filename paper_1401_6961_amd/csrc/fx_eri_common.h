@@ -146,6 +146,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
     const long slot_unit = (long)blockIdx.x * WAVES + wave;
     if (slot_unit >= A.nunits) return;
     const int u = __builtin_amdgcn_readfirstlane(A.order ? A.order[slot_unit] : (int)slot_unit);
+    const uint64_t t_start = A.times ? wall_clock64() : 0;
     const int item = __builtin_amdgcn_readfirstlane(A.units[3 * u]);
     const int a = __builtin_amdgcn_readfirstlane(A.units[3 * u + 1]);
     const int d = __builtin_amdgcn_readfirstlane(A.units[3 * u + 2]);
@@ -264,6 +265,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
         }
     }
     if (lane < NA * ND) A.kslot[rowbase + (long)(lane / ND) * A.n + (lane % ND)] = outv;
+    if (A.times && lane == 0) A.times[u] = (float)(wall_clock64() - t_start);
     if (A.counters) {
         long np = npq;
 #pragma unroll

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <numeric>
 #include <string>
@@ -324,10 +325,37 @@ struct fx_tree {
     double* boys = nullptr;
     std::vector<int*> d_sL, d_sR, d_ch0, d_nch;
     std::vector<double*> d_Qsq;      // per level (nk x nk)
+    double* qrow = nullptr;          // max_b Qn[s][b]
+    float mean_np[3] = {1, 1, 1};    // mean primitive count of the shells of each l
     ~fx_tree() {
         if (arena) (void)hipDeviceSynchronize();
         delete arena;
     }
+};
+
+struct fx_costmodel {
+    std::vector<float> W, norm;    // FX_MLP_NPARAM, FX_MLP_NNORM
+    float* dW = nullptr;
+    float* dnorm = nullptr;
+    ~fx_costmodel() {
+        if (dW) (void)hipFree(dW);
+        if (dnorm) (void)hipFree(dnorm);
+    }
+    void upload() {
+        if (!dW) {
+            if (hipMalloc(&dW, sizeof(float) * FX_MLP_NPARAM) != hipSuccess ||
+                hipMalloc(&dnorm, sizeof(float) * FX_MLP_NNORM) != hipSuccess)
+                fx_fail(FX_ERR_OOM, "cost model allocation failed");
+        }
+        FX_HIP(hipMemcpy(dW, W.data(), sizeof(float) * FX_MLP_NPARAM, hipMemcpyHostToDevice));
+        FX_HIP(hipMemcpy(dnorm, norm.data(), sizeof(float) * FX_MLP_NNORM, hipMemcpyHostToDevice));
+    }
+};
+
+struct fx_task_timings {
+    std::vector<float> feat;    // 4 per sample
+    std::vector<float> log2ns;  // measured unit time
+    std::vector<int> cls;       // cls * 2 + fp32
 };
 
 static void build_tree(const fx_shells* s, const fx_tree_opts* opts, hipStream_t st, fx_tree* T) {
@@ -446,6 +474,16 @@ static void build_tree(const fx_shells* s, const fx_tree_opts* opts, hipStream_t
         FX_HIP(hipGetLastError());
         FX_HIP(hipStreamSynchronize(st));
     }
+    T->qrow = A.get<double>(S);
+    fx_launch_qrow(Qn, S, T->qrow, st);
+    {
+        double sum[3] = {0, 0, 0}, cnt[3] = {0, 0, 0};
+        for (int t = 0; t < S; ++t) {
+            sum[l[t]] += np[t];
+            cnt[l[t]] += 1;
+        }
+        for (int L = 0; L < 3; ++L) T->mean_np[L] = cnt[L] > 0 ? (float)(sum[L] / cnt[L]) : 1.f;
+    }
     // squared block norms of Q at every level
     const int nl = (int)P.levels.size();
     T->d_Qsq.resize(nl);
@@ -507,12 +545,16 @@ struct ExCtx {
     long* scan_total;
     double seconds_eri = 0;
     int profile = 0;
+    fx_task_timings* rec = nullptr;   // timing-probe collection
+    double tick_ns = 10.0;            // wall-clock tick
     struct Timed {
         int idx;
         hipEvent_t a, b;
     };
     std::vector<Timed> timed;
 };
+
+static thread_local fx_task_timings* g_recording = nullptr;
 
 static int slot_index(const ExCtx& c, int lb, int lc, int prec32) {
     const int L = c.T->lmax + 1;
@@ -568,6 +610,31 @@ static void leaf_work(ExCtx& c, const Frontier& f) {
     args.tau = c.tau;
     args.thr = c.thr;
     const int Lm = T->lmax;
+    long maxlist = 0;
+    for (int k = 0; k < 9; ++k) maxlist = std::max(maxlist, bounds[k + 1] - bounds[k]);
+    const bool sched = c.schedule != FX_SCHED_NONE;
+    const bool use_mlp = c.schedule == FX_SCHED_MLP && c.cm;
+    const int nbins = 32;
+    float4* feat = nullptr;
+    float* cost = nullptr;
+    int* flags = nullptr;
+    uint8_t* key = nullptr;
+    long* bpos = nullptr;
+    int* order = nullptr;
+    float* times = nullptr;
+    if ((sched || c.rec) && maxlist > 0) {
+        feat = A.get<float4>(maxlist);
+        cost = A.get<float>(maxlist);
+        if (sched) {
+            flags = A.get<int>((size_t)nbins * maxlist);
+            key = A.get<uint8_t>(maxlist);
+            bpos = A.get<long>((size_t)nbins * maxlist + 1);
+            order = A.get<int>(maxlist);
+        }
+        if (c.rec) times = A.get<float>(maxlist);
+    }
+    long* bpartial = sched ? A.get<long>(fx_scan_tiles((long)nbins * std::max(1L, maxlist))) : nullptr;
+    std::vector<float> hfeat, htime;
     for (int la = 0; la <= Lm; ++la)
         for (int ld = 0; ld <= Lm; ++ld) {
             const int cls2 = la * 3 + ld;
@@ -580,7 +647,27 @@ static void leaf_work(ExCtx& c, const Frontier& f) {
                 for (int lc = 0; lc <= Lm; ++lc) {
                     const int cls = ((la * 3 + lb) * 3 + lc) * 3 + ld;
                     const int nprec = c.precision == FX_PREC_MIXED ? 2 : 1;
+                    const float class_cost = std::log2(
+                        (float)fx_class_vrr_flops[cls] * T->mean_np[lb] * T->mean_np[lc] + (float)fx_class_hrr_flops[cls] + 1.f);
+                    args.order = nullptr;
+                    args.times = nullptr;
+                    if (feat) {
+                        fx_launch_unit_features(args.units, args.nunits, f.bc_off, args.cls_off, lb * 3 + lc,
+                                                T->basis.nprim, T->qrow, class_cost, feat, st);
+                    }
+                    if (sched) {
+                        // predicted log2 cost per unit: the learned model, or the
+                        // bound-only estimate log2(class flops * nprim_a nprim_d * entries)
+                        if (use_mlp)
+                            fx_launch_mlp_predict(c.cm->dW, c.cm->dnorm, feat, args.nunits, cost, st);
+                        else
+                            fx_launch_bound_cost(feat, args.nunits, cost, st);
+                        fx_launch_bin_order(cost, args.nunits, use_mlp ? 40.f : 48.f, 1.0f, nbins, flags, key, bpos,
+                                            bpartial, c.scan_total, order, st, fx_scan_i32);
+                        args.order = order;
+                    }
                     for (int pr = 0; pr < nprec; ++pr) {
+                        if (c.rec) args.times = times;
                         args.mode = c.precision == FX_PREC_MIXED ? (pr ? FX_MODE_MIXED_LO : FX_MODE_MIXED_HI)
                                                                  : FX_MODE_ALL;
                         args.kslot = c.slots + (long)slot_index(c, lb, lc, pr) * T->n * T->n;
@@ -595,6 +682,19 @@ static void leaf_work(ExCtx& c, const Frontier& f) {
                             c.timed.push_back(t);
                         } else {
                             fx_class_table[cls](pr, g_variant[cls][pr], args, st);
+                        }
+                        if (c.rec) {
+                            const long n = args.nunits;
+                            hfeat.resize(4 * n);
+                            htime.resize(n);
+                            FX_HIP(hipMemcpyAsync(hfeat.data(), feat, sizeof(float4) * n, hipMemcpyDeviceToHost, st));
+                            FX_HIP(hipMemcpyAsync(htime.data(), times, sizeof(float) * n, hipMemcpyDeviceToHost, st));
+                            FX_HIP(hipStreamSynchronize(st));
+                            for (long u = 0; u < n; ++u) {
+                                for (int q = 0; q < 4; ++q) c.rec->feat.push_back(hfeat[4 * u + q]);
+                                c.rec->log2ns.push_back(std::log2(std::max(1.0, (double)htime[u] * c.tick_ns)));
+                                c.rec->cls.push_back(cls * 2 + pr);
+                            }
                         }
                     }
                 }
@@ -730,6 +830,14 @@ static void exchange_impl(const fx_tree* T, const double* P, double tau, double*
     c.cap = o.max_frontier_entries > 0 ? o.max_frontier_entries : (1L << 30);
     c.stats = stats;
     c.profile = o.profile;
+    c.rec = g_recording;
+    if (c.rec) {
+        int dev = 0, khz = 0;
+        FX_HIP(hipGetDevice(&dev));
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            c.tick_ns = 1e6 / (double)khz;
+    }
+    if (o.schedule == FX_SCHED_MLP && !o.costmodel) c.schedule = FX_SCHED_BOUND;
     // density norms
     c.Pn = A.get<double>((size_t)S * S);
     fx_launch_pnorm(P, n, T->basis.l, T->basis.f0, S, c.Pn, st);
@@ -934,6 +1042,218 @@ int32_t fx_get_class_variant(int32_t cls, int32_t prec32) {
 int32_t fx_class_variants_available(int32_t cls) {
     if (cls < 0 || cls >= 81) return 0;
     return fx_class_variants[cls];
+}
+
+fx_status fx_record_task_timings(const fx_tree* tree, const double* P, double tau, const fx_exchange_opts* opts,
+                                 fx_task_timings** out, void* stream) {
+    return fx_guard([&] {
+        if (!out) fx_fail(FX_ERR_INVALID_ARG, "out is NULL");
+        *out = nullptr;
+        if (!tree) fx_fail(FX_ERR_INVALID_ARG, "tree is NULL");
+        hipStream_t st = (hipStream_t)stream;
+        DevArena A(st);
+        double* K = A.get<double>((size_t)tree->n * tree->n);
+        fx_task_timings* rec = new fx_task_timings();
+        g_recording = rec;
+        try {
+            exchange_impl(tree, P, tau, K, opts, nullptr, st);
+        } catch (...) {
+            g_recording = nullptr;
+            delete rec;
+            throw;
+        }
+        g_recording = nullptr;
+        *out = rec;
+    });
+}
+
+fx_status fx_task_timings_create(const float* feats, const float* log2_ns, const int32_t* cls, int64_t n,
+                                 fx_task_timings** out) {
+    return fx_guard([&] {
+        if (!out || n < 0 || (n > 0 && (!feats || !log2_ns))) fx_fail(FX_ERR_INVALID_ARG, "bad arguments");
+        fx_task_timings* t = new fx_task_timings();
+        t->feat.assign(feats, feats + 4 * n);
+        t->log2ns.assign(log2_ns, log2_ns + n);
+        t->cls.resize(n, -1);
+        if (cls)
+            for (int64_t i = 0; i < n; ++i) t->cls[i] = cls[i];
+        *out = t;
+    });
+}
+
+int64_t fx_task_timings_count(const fx_task_timings* t) { return t ? (int64_t)t->log2ns.size() : -1; }
+
+fx_status fx_task_timings_get(const fx_task_timings* t, float* feats, float* log2_ns, int32_t* cls) {
+    return fx_guard([&] {
+        if (!t) fx_fail(FX_ERR_INVALID_ARG, "timings is NULL");
+        if (feats) std::copy(t->feat.begin(), t->feat.end(), feats);
+        if (log2_ns) std::copy(t->log2ns.begin(), t->log2ns.end(), log2_ns);
+        if (cls) std::copy(t->cls.begin(), t->cls.end(), cls);
+    });
+}
+
+void fx_task_timings_free(fx_task_timings* t) { delete t; }
+
+fx_status fx_costmodel_create(const float* params, const float* norm, fx_costmodel** out) {
+    return fx_guard([&] {
+        if (!params || !norm || !out) fx_fail(FX_ERR_INVALID_ARG, "NULL argument");
+        fx_costmodel* m = new fx_costmodel();
+        m->W.assign(params, params + FX_MLP_NPARAM);
+        m->norm.assign(norm, norm + FX_MLP_NNORM);
+        try {
+            m->upload();
+        } catch (...) {
+            delete m;
+            throw;
+        }
+        *out = m;
+    });
+}
+
+fx_status fx_costmodel_params(const fx_costmodel* m, float* params, float* norm) {
+    return fx_guard([&] {
+        if (!m) fx_fail(FX_ERR_INVALID_ARG, "model is NULL");
+        if (params) std::copy(m->W.begin(), m->W.end(), params);
+        if (norm) std::copy(m->norm.begin(), m->norm.end(), norm);
+    });
+}
+
+void fx_costmodel_free(fx_costmodel* m) { delete m; }
+
+int32_t fx_costmodel_nparams(void) { return FX_MLP_NPARAM; }
+
+fx_status fx_costmodel_predict(const fx_costmodel* m, const float* feats, int64_t n, float* out, void* stream) {
+    return fx_guard([&] {
+        if (!m || (n > 0 && (!feats || !out))) fx_fail(FX_ERR_INVALID_ARG, "NULL argument");
+        if (n == 0) return;
+        hipStream_t st = (hipStream_t)stream;
+        DevArena A(st);
+        float4* f = A.get<float4>(n);
+        float* y = A.get<float>(n);
+        FX_HIP(hipMemcpyAsync(f, feats, sizeof(float4) * n, hipMemcpyHostToDevice, st));
+        fx_launch_mlp_predict(m->dW, m->dnorm, f, n, y, st);
+        FX_HIP(hipMemcpyAsync(out, y, sizeof(float) * n, hipMemcpyDeviceToHost, st));
+        FX_HIP(hipStreamSynchronize(st));
+    });
+}
+
+// loss = mean((y - t)^2) on standardised targets, and its gradient
+static void mlp_loss_grad_dev(const fx_costmodel* m, const float4* f, const float* t, const int* idx, long n, float* act,
+                              float* lterm, float* grad, float* loss, hipStream_t st) {
+    fx_mlp_backprop_grad(m->dW, m->dnorm, f, t, idx, n, act, lterm, grad, loss, st);
+}
+
+fx_status fx_costmodel_loss_grad(const fx_costmodel* m, const float* feats, const float* log2_ns, int64_t n,
+                                 float* loss, float* grad, void* stream) {
+    return fx_guard([&] {
+        if (!m || n <= 0 || !feats || !log2_ns) fx_fail(FX_ERR_INVALID_ARG, "bad arguments");
+        hipStream_t st = (hipStream_t)stream;
+        DevArena A(st);
+        float4* f = A.get<float4>(n);
+        float* t = A.get<float>(n);
+        float* act = A.get<float>((size_t)n * FX_MLP_ACT);
+        float* lt = A.get<float>(n);
+        float* g = A.get<float>(FX_MLP_NPARAM);
+        float* l = A.get<float>(1);
+        FX_HIP(hipMemcpyAsync(f, feats, sizeof(float4) * n, hipMemcpyHostToDevice, st));
+        FX_HIP(hipMemcpyAsync(t, log2_ns, sizeof(float) * n, hipMemcpyHostToDevice, st));
+        mlp_loss_grad_dev(m, f, t, nullptr, n, act, lt, g, l, st);
+        if (grad) FX_HIP(hipMemcpyAsync(grad, g, sizeof(float) * FX_MLP_NPARAM, hipMemcpyDeviceToHost, st));
+        if (loss) FX_HIP(hipMemcpyAsync(loss, l, sizeof(float), hipMemcpyDeviceToHost, st));
+        FX_HIP(hipStreamSynchronize(st));
+    });
+}
+
+// Train a cost model on GPU: standardise inputs and targets, Glorot-uniform
+// initialisation from a seeded generator, Adam on seeded minibatches.
+fx_status fx_costmodel_train(const fx_task_timings* data, const fx_train_opts* opts, fx_costmodel** out,
+                             float* final_loss, void* stream) {
+    return fx_guard([&] {
+        if (!data || !out) fx_fail(FX_ERR_INVALID_ARG, "NULL argument");
+        const long n = (long)data->log2ns.size();
+        if (n < 8) fx_fail(FX_ERR_INVALID_ARG, "need at least 8 samples");
+        fx_train_opts o{2000, 8192, 3e-3f, 12345};
+        if (opts) o = *opts;
+        if (o.steps <= 0 || o.batch <= 0 || !(o.lr > 0.f)) fx_fail(FX_ERR_INVALID_ARG, "bad training options");
+        hipStream_t st = (hipStream_t)stream;
+        fx_costmodel* m = new fx_costmodel();
+        std::unique_ptr<fx_costmodel> guard(m);
+        m->norm.assign(FX_MLP_NNORM, 0.f);
+        for (int k = 0; k < 4; ++k) {
+            double mu = 0, s2 = 0;
+            for (long i = 0; i < n; ++i) mu += data->feat[4 * i + k];
+            mu /= n;
+            for (long i = 0; i < n; ++i) s2 += (data->feat[4 * i + k] - mu) * (data->feat[4 * i + k] - mu);
+            m->norm[k] = (float)mu;
+            m->norm[4 + k] = (float)std::max(1e-3, std::sqrt(s2 / n));
+        }
+        {
+            double mu = 0, s2 = 0;
+            for (long i = 0; i < n; ++i) mu += data->log2ns[i];
+            mu /= n;
+            for (long i = 0; i < n; ++i) s2 += (data->log2ns[i] - mu) * (data->log2ns[i] - mu);
+            m->norm[8] = (float)mu;
+            m->norm[9] = (float)std::max(1e-3, std::sqrt(s2 / n));
+        }
+        // splitmix64 stream for initialisation and minibatches
+        uint64_t state = o.seed;
+        auto next = [&]() {
+            uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            return z ^ (z >> 31);
+        };
+        auto unif = [&]() { return (double)(next() >> 11) * (1.0 / 9007199254740992.0); };
+        m->W.assign(FX_MLP_NPARAM, 0.f);
+        auto glorot = [&](int off, int fan_in, int fan_out) {
+            const double a = std::sqrt(6.0 / (fan_in + fan_out));
+            for (int i = 0; i < fan_in * fan_out; ++i) m->W[off + i] = (float)((2 * unif() - 1) * a);
+        };
+        glorot(FX_MLP_W1, FX_MLP_IN, FX_MLP_H);
+        glorot(FX_MLP_W2, FX_MLP_H, FX_MLP_H);
+        glorot(FX_MLP_W3, FX_MLP_H, 1);
+        m->upload();
+        DevArena A(st);
+        const long B = std::min<long>(o.batch, n);
+        float4* f = A.get<float4>(n);
+        float* t = A.get<float>(n);
+        float* act = A.get<float>((size_t)std::max(B, n < 65536 ? n : B) * FX_MLP_ACT);
+        float* lt = A.get<float>(std::max(B, n));
+        float* g = A.get<float>(FX_MLP_NPARAM);
+        float* mo = A.get<float>(FX_MLP_NPARAM);
+        float* vo = A.get<float>(FX_MLP_NPARAM);
+        float* l = A.get<float>(1);
+        int* idx = A.get<int>(B);
+        FX_HIP(hipMemcpyAsync(f, data->feat.data(), sizeof(float) * 4 * n, hipMemcpyHostToDevice, st));
+        FX_HIP(hipMemcpyAsync(t, data->log2ns.data(), sizeof(float) * n, hipMemcpyHostToDevice, st));
+        FX_HIP(hipMemsetAsync(mo, 0, sizeof(float) * FX_MLP_NPARAM, st));
+        FX_HIP(hipMemsetAsync(vo, 0, sizeof(float) * FX_MLP_NPARAM, st));
+        std::vector<int> hidx(B);
+        for (int step = 1; step <= o.steps; ++step) {
+            for (long i = 0; i < B; ++i) hidx[i] = B == n ? (int)i : (int)(next() % (uint64_t)n);
+            FX_HIP(hipMemcpyAsync(idx, hidx.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+            mlp_loss_grad_dev(m, f, t, idx, B, act, lt, g, l, st);
+            fx_mlp_adam(m->dW, g, mo, vo, o.lr, step, st);
+            FX_HIP(hipStreamSynchronize(st));   // idx host buffer is reused next step
+        }
+        FX_HIP(hipMemcpyAsync(m->W.data(), m->dW, sizeof(float) * FX_MLP_NPARAM, hipMemcpyDeviceToHost, st));
+        if (final_loss) {
+            // loss over the whole data set (minibatches of the activation buffer size)
+            const long chunk = n < 65536 ? n : B;
+            double acc = 0;
+            for (long s0 = 0; s0 < n; s0 += chunk) {
+                const long cn = std::min(chunk, n - s0);
+                float lv = 0.f;
+                mlp_loss_grad_dev(m, f + s0, t + s0, nullptr, cn, act, lt, g, l, st);
+                FX_HIP(hipMemcpyAsync(&lv, l, sizeof(float), hipMemcpyDeviceToHost, st));
+                FX_HIP(hipStreamSynchronize(st));
+                acc += (double)lv * cn;
+            }
+            *final_loss = (float)(acc / n);
+        }
+        FX_HIP(hipStreamSynchronize(st));
+        *out = guard.release();
+    });
 }
 
 // Host-only planning (no device work): the tree order and the bisection

@@ -58,6 +58,7 @@ struct FxClassArgs {
     int mode;                         // FX_MODE_*
     double* kslot;                    // n*n slot for this (lb, lc, precision)
     unsigned long long* counters;     // computed quartets (nullable)
+    float* times;                     // per-unit wall-clock ticks (nullable; timing probes)
 };
 
 // Launchers defined in the generated class files.

@@ -42,6 +42,11 @@ class fx_exchange_opts(ctypes.Structure):
                 ("max_frontier_entries", ctypes.c_int64), ("profile", ctypes.c_int32)]
 
 
+class fx_train_opts(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
 class fx_stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("frontier", ctypes.c_int64 * 32),
                 ("leaf_items", ctypes.c_int64), ("units", ctypes.c_int64),
@@ -70,7 +75,10 @@ class fx_stats(ctypes.Structure):
 EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_batched", "fx_nbf", "fx_nshell",
             "fx_tree_perm", "fx_tree_levels", "fx_tree_schwarz", "fx_tree_free", "fx_set_allocator",
             "fx_status_string", "fx_last_error_message", "fx_plan_tree", "fx_hilbert_key3",
-            "fx_set_class_variant", "fx_get_class_variant", "fx_class_variants_available"]
+            "fx_set_class_variant", "fx_get_class_variant", "fx_class_variants_available",
+            "fx_record_task_timings", "fx_task_timings_create", "fx_task_timings_count", "fx_task_timings_get",
+            "fx_task_timings_free", "fx_costmodel_train", "fx_costmodel_nparams", "fx_costmodel_create",
+            "fx_costmodel_params", "fx_costmodel_predict", "fx_costmodel_loss_grad", "fx_costmodel_free"]
 
 
 def lib():
@@ -114,6 +122,25 @@ def lib():
     L.fx_get_class_variant.restype = i32
     L.fx_class_variants_available.argtypes = [i32]
     L.fx_class_variants_available.restype = i32
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.fx_record_task_timings.argtypes = [vp, vp, dbl, ctypes.POINTER(fx_exchange_opts), ctypes.POINTER(vp), vp]
+    L.fx_task_timings_create.argtypes = [fp, fp, ctypes.POINTER(i32), i64, ctypes.POINTER(vp)]
+    L.fx_task_timings_count.argtypes = [vp]
+    L.fx_task_timings_count.restype = i64
+    L.fx_task_timings_get.argtypes = [vp, fp, fp, ctypes.POINTER(i32)]
+    L.fx_task_timings_free.argtypes = [vp]
+    L.fx_task_timings_free.restype = None
+    L.fx_costmodel_train.argtypes = [vp, ctypes.POINTER(fx_train_opts), ctypes.POINTER(vp), fp, vp]
+    L.fx_costmodel_nparams.restype = i32
+    L.fx_costmodel_create.argtypes = [fp, fp, ctypes.POINTER(vp)]
+    L.fx_costmodel_params.argtypes = [vp, fp, fp]
+    L.fx_costmodel_predict.argtypes = [vp, fp, i64, fp, vp]
+    L.fx_costmodel_loss_grad.argtypes = [vp, fp, fp, i64, fp, fp, vp]
+    L.fx_costmodel_free.argtypes = [vp]
+    L.fx_costmodel_free.restype = None
+    for f in ("fx_record_task_timings", "fx_task_timings_create", "fx_task_timings_get", "fx_costmodel_train",
+              "fx_costmodel_create", "fx_costmodel_params", "fx_costmodel_predict", "fx_costmodel_loss_grad"):
+        getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
 
@@ -294,3 +321,115 @@ def fx_get_class_variant(cls, prec32):
 
 def fx_class_variants_available(cls):
     return int(lib().fx_class_variants_available(int(cls)))
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class TaskTimings:
+    """(features, log2 ns) samples of K-block work units."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __len__(self):
+        return int(lib().fx_task_timings_count(self._h))
+
+    def arrays(self):
+        n = len(self)
+        f = np.zeros((n, 4), np.float32)
+        t = np.zeros(n, np.float32)
+        c = np.zeros(n, np.int32)
+        _check(lib().fx_task_timings_get(self._h, _fptr(f), _fptr(t), c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return f, t, c
+
+    @staticmethod
+    def from_arrays(feats, log2_ns, cls=None):
+        f = np.ascontiguousarray(feats, np.float32).reshape(-1, 4)
+        t = np.ascontiguousarray(log2_ns, np.float32)
+        c = None if cls is None else np.ascontiguousarray(cls, np.int32)
+        h = ctypes.c_void_p()
+        _check(lib().fx_task_timings_create(_fptr(f), _fptr(t),
+                                            None if c is None else c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                            len(t), ctypes.byref(h)))
+        return TaskTimings(h.value)
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().fx_task_timings_free(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+class CostModel:
+    """Handle of a trained MLP cost model."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def params(self):
+        n = int(lib().fx_costmodel_nparams())
+        w = np.zeros(n, np.float32)
+        norm = np.zeros(10, np.float32)
+        _check(lib().fx_costmodel_params(self._h, _fptr(w), _fptr(norm)))
+        return w, norm
+
+    @staticmethod
+    def create(params, norm):
+        w = np.ascontiguousarray(params, np.float32)
+        nm = np.ascontiguousarray(norm, np.float32)
+        h = ctypes.c_void_p()
+        _check(lib().fx_costmodel_create(_fptr(w), _fptr(nm), ctypes.byref(h)))
+        return CostModel(h.value)
+
+    def predict(self, feats, stream=None):
+        f = np.ascontiguousarray(feats, np.float32).reshape(-1, 4)
+        out = np.zeros(len(f), np.float32)
+        _check(lib().fx_costmodel_predict(self._h, _fptr(f), len(f), _fptr(out), _stream_ptr(stream)))
+        return out
+
+    def loss_grad(self, feats, log2_ns, stream=None):
+        f = np.ascontiguousarray(feats, np.float32).reshape(-1, 4)
+        t = np.ascontiguousarray(log2_ns, np.float32)
+        g = np.zeros(int(lib().fx_costmodel_nparams()), np.float32)
+        loss = np.zeros(1, np.float32)
+        _check(lib().fx_costmodel_loss_grad(self._h, _fptr(f), _fptr(t), len(t), _fptr(loss), _fptr(g),
+                                            _stream_ptr(stream)))
+        return float(loss[0]), g
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().fx_costmodel_free(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def fx_record_task_timings(tree, P, tau, opts=None, stream=None) -> TaskTimings:
+    _check_matrix(P, tree.nbf, "P")
+    o = opts if opts is not None else make_opts()
+    h = ctypes.c_void_p()
+    _check(lib().fx_record_task_timings(tree.handle, ctypes.c_void_p(P.data_ptr()), float(tau), ctypes.byref(o),
+                                        ctypes.byref(h), _stream_ptr(stream)))
+    return TaskTimings(h.value)
+
+
+def fx_costmodel_train(timings, steps=2000, batch=8192, lr=3e-3, seed=12345, stream=None):
+    o = fx_train_opts(int(steps), int(batch), float(lr), int(seed))
+    h = ctypes.c_void_p()
+    loss = ctypes.c_float()
+    _check(lib().fx_costmodel_train(timings.handle, ctypes.byref(o), ctypes.byref(h), ctypes.byref(loss),
+                                    _stream_ptr(stream)))
+    return CostModel(h.value), float(loss.value)
