@@ -109,6 +109,7 @@ typedef struct fx_exchange_opts {
     double alpha, beta;         /* K <- alpha*K_x + beta*K; default 1, 0     */
     int64_t max_frontier_entries; /* traversal chunking threshold, 0 = auto  */
     int32_t profile;            /* 1: time every class-kernel launch with HIP events on `stream` */
+    int32_t use_graph;          /* 1: capture the class-kernel launch sequence in a hipGraph and launch it */
 } fx_exchange_opts;
 
 /* Statistics of one fx_exchange_ex call (valid when the call returns). */
@@ -124,6 +125,7 @@ typedef struct fx_stats {
     double prim_quartets;                        /* primitive quartets        */
     double flops;                                /* algorithmic flops (generated-code count) */
     int32_t chunks;                              /* traversal chunks          */
+    int32_t graph_nodes;                         /* graphs launched           */
     /* with opts.profile: per class and precision (index cls*2 + fp32) */
     double class_seconds[162];                   /* summed kernel time (HIP events) */
     int32_t class_launches[162];                 /* launches                   */
@@ -152,8 +154,10 @@ fx_status fx_exchange_ex(const fx_tree* tree, const double* P, double tau, doubl
                          const fx_exchange_opts* opts, fx_stats* stats, void* stream);
 
 /* Many independent systems in one call: trees[i], P[i], K[i] (host arrays of
- * device pointers), all with the same tau and options.  The work of all
- * systems shares one traversal per level and one launch per class. */
+ * device pointers), all with the same tau and options.  Every system is
+ * traversed, then each class kernel is launched once over the K-block units
+ * of all systems (per-unit system descriptors), optionally captured in a
+ * hipGraph (opts.use_graph).  Each K[i] equals fx_exchange_ex's result. */
 fx_status fx_exchange_batched(const fx_tree* const* trees, const double* const* P, double* const* K,
                               int32_t count, double tau, const fx_exchange_opts* opts,
                               fx_stats* stats, void* stream);
@@ -223,6 +227,16 @@ void fx_costmodel_free(fx_costmodel* m);
  * quartet set and agree to rounding.  Process-wide setting. */
 fx_status fx_set_class_variant(int32_t cls, int32_t prec32, int32_t variant);
 int32_t fx_get_class_variant(int32_t cls, int32_t prec32);
+/* Launch flags of a class and precision: bit 0 = XCD-aware workgroup remap
+ * (neighbouring K blocks, which share density and pair data, on one XCD and
+ * its L2).  Bit 1 (persistent grid pulling units from an atomic counter) is
+ * switched off and returns FX_ERR_UNSUPPORTED.  Chosen by the autotuner; K
+ * does not depend on them. */
+fx_status fx_set_class_launch(int32_t cls, int32_t prec32, int32_t flags);
+int32_t fx_get_class_launch(int32_t cls, int32_t prec32);
+/* Logical block of hardware workgroup b of nb under the XCD remap (-1 if out
+ * of range); host-callable so the mapping can be checked. */
+int64_t fx_xcd_block(int64_t b, int64_t nb);
 /* Bit mask of the variants built for a class (bit 0 thread, bit 1 wave). */
 int32_t fx_class_variants_available(int32_t cls);
 

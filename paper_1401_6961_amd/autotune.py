@@ -1,0 +1,97 @@
+"""Autotuner of the class kernels.
+
+For every angular-momentum class and precision it chooses the kernel form
+(one quartet per lane, or one quartet per wave with LDS intermediates, where
+both are built) and the launch mapping (plain or XCD-aware workgroup order)
+that run fastest on a representative workload.  Each candidate setting is
+applied to all classes at once, the workload is built with per-launch HIP
+event timing, and the fastest setting per (class, precision) wins.  K does
+not depend on these choices (tests check this bitwise).
+
+    python -m paper_1401_6961_amd.autotune --natom 300 --out tuning_gfx950.json
+
+apply(path) loads a table into the library (process-wide).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_TABLE = os.path.join(HERE, "tuning_gfx950.json")
+
+
+def apply(path: str = DEFAULT_TABLE) -> int:
+    """Load a tuning table; returns the number of (class, precision) entries set."""
+    from . import fx
+    if not os.path.exists(path):
+        return 0
+    table = json.load(open(path))
+    n = 0
+    for key, ent in table.get("classes", {}).items():
+        cls, prec = (int(x) for x in key.split(":"))
+        if fx.fx_class_variants_available(cls) & (1 << ent["variant"]):
+            fx.fx_set_class_variant(cls, prec, ent["variant"])
+        fx.fx_set_class_launch(cls, prec, ent["flags"])
+        n += 1
+    return n
+
+
+def tune(natom=300, with_d=True, seed=1002, repeats=2, log=print):
+    import numpy as np
+    import torch
+
+    import synthetic
+    from . import fx
+
+    system = synthetic.cluster(natom, seed=seed, with_d=with_d)
+    tree = fx.build_quadtree_from(system)
+    P = torch.from_numpy(system.P).cuda()
+    K = torch.zeros_like(P)
+    configs = [(v, f) for v in (0, 1) for f in (0, 1)]
+    times = {}
+    for v, f in configs:
+        for cls in range(81):
+            for p in (0, 1):
+                if fx.fx_class_variants_available(cls) & (1 << v):
+                    fx.fx_set_class_variant(cls, p, v)
+                else:
+                    fx.fx_set_class_variant(cls, p, 0 if v else 1)
+                fx.fx_set_class_launch(cls, p, f)
+        best = None
+        for _ in range(repeats):
+            _, st = fx.fx_exchange_ex(tree, P, system.tau, K, fx.make_opts(precision=fx.FX_PREC_MIXED, profile=True))
+            cs = st["class_seconds"]
+            best = cs if best is None else np.minimum(best, cs)
+        times[(v, f)] = best
+        log(f"autotune: variant={v} xcd={f} total class time {best.sum():.3f} s")
+    table = {"workload": f"{natom}-atom {'s+p+d' if with_d else 's+p'} cluster, mixed precision",
+             "device": torch.cuda.get_device_name(0), "classes": {}}
+    for cls in range(81):
+        for p in (0, 1):
+            cands = [(times[(v, f)][cls, p], v, f) for (v, f) in configs
+                     if fx.fx_class_variants_available(cls) & (1 << v) and times[(v, f)][cls, p] > 0]
+            if not cands:
+                continue
+            t, v, f = min(cands)
+            table["classes"][f"{cls}:{p}"] = {"variant": v, "flags": f, "ms": 1e3 * float(t)}
+    return table
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--natom", type=int, default=300)
+    ap.add_argument("--sp", action="store_true", help="s+p shells only")
+    ap.add_argument("--out", default=DEFAULT_TABLE)
+    args = ap.parse_args()
+    table = tune(args.natom, with_d=not args.sp, log=lambda m: print(m, flush=True))
+    with open(args.out, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+    print(f"autotune: wrote {len(table['classes'])} entries to {args.out}", flush=True)
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, os.path.dirname(HERE))
+    main()

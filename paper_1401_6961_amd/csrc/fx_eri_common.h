@@ -137,20 +137,19 @@ __device__ __forceinline__ double fx_comp_factor(int l, int k) {
 // once to this class's (lb, lc, precision) slot: no atomics.
 // ---------------------------------------------------------------------------
 template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, typename Fn>
-__device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
+__device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, long slot_unit, int wave,
+                                              int2 (*queue)[128]) {
     constexpr int NA = fx_ncart(LA), ND = fx_ncart(LD);
     constexpr int NK = COOP ? 1 : NA * ND;   // K elements held per lane
-    __shared__ int2 queue[WAVES][128];
     const int lane = fx_lane();
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const long slot_unit = (long)blockIdx.x * WAVES + wave;
-    if (slot_unit >= A.nunits) return;
     const int u = __builtin_amdgcn_readfirstlane(A.order ? A.order[slot_unit] : (int)slot_unit);
+    const int sid = A.unit_sys ? __builtin_amdgcn_readfirstlane(A.unit_sys[u]) : -1;
+    const FxSys Sy = sid >= 0 ? A.sys[sid] : A.one;
     const uint64_t t_start = A.times ? wall_clock64() : 0;
     const int item = __builtin_amdgcn_readfirstlane(A.units[3 * u]);
     const int a = __builtin_amdgcn_readfirstlane(A.units[3 * u + 1]);
     const int d = __builtin_amdgcn_readfirstlane(A.units[3 * u + 2]);
-    const FxDevBasis& Bs = A.basis;
+    const FxDevBasis& Bs = Sy.basis;
     const int S = Bs.nshell;
     const FxShellRef ra = fx_shell(Bs, a), rd = fx_shell(Bs, d);
     const double* __restrict__ Qa = Bs.Qn + (long)a * S;
@@ -161,17 +160,17 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
 #pragma unroll
     for (int i = 0; i < NK; ++i) kacc[i] = 0.0;
 
-    const long e0 = A.bc_off[item], e1 = A.bc_off[item + 1];
+    const long e0 = Sy.bc_off[item], e1 = Sy.bc_off[item + 1];
     int qn = 0;
     long nq = 0, npq = 0;
     auto evaluate = [&](int2 q) {
         const FxShellRef rb = fx_shell(Bs, q.x), rc = fx_shell(Bs, q.y);
         if (!COOP || lane == 0) npq += (long)(ra.nprim * rb.nprim) * (rc.nprim * rd.nprim);
-        const double* Pblk = A.P + (long)Bs.f0[q.x] * A.n + Bs.f0[q.y];
-        fn(ra, rb, rc, rd, Bs, A.boys, Pblk, A.n, kacc, wave);
+        const double* Pblk = Sy.P + (long)Bs.f0[q.x] * Sy.n + Bs.f0[q.y];
+        fn(ra, rb, rc, rd, Bs, A.boys, Pblk, Sy.n, kacc, wave);
     };
     auto test = [&](int b, int c) {
-        const double beta = (Qa[b] * Qd[c]) * A.Pn[(long)b * S + c];
+        const double beta = (Qa[b] * Qd[c]) * Sy.Pn[(long)b * S + c];
         bool ok = beta > tau;
         if (mode == FX_MODE_MIXED_HI) ok = ok && !(beta < thr);
         else if (mode == FX_MODE_MIXED_LO) ok = ok && (beta < thr);
@@ -184,9 +183,9 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
     };
     // Candidate cursor: single-shell leaves read the item's (lb, lc) segment
     // (leaf index == shell index); larger leaves enumerate b in B, c in C.
-    const bool seg = A.cls_off != nullptr;
-    long cur = seg ? A.cls_off[(long)item * 10 + LB * 3 + LC] : e0;
-    const long cend = seg ? A.cls_off[(long)item * 10 + LB * 3 + LC + 1] : e1;
+    const bool seg = Sy.cls_off != nullptr;
+    long cur = seg ? Sy.cls_off[(long)item * 10 + LB * 3 + LC] : e0;
+    const long cend = seg ? Sy.cls_off[(long)item * 10 + LB * 3 + LC + 1] : e1;
     int kc = 0, maxc = 0, nb = 0, nc = 0, ob = 0, oc = 0;
     while (true) {
         // fill: screen candidates until a full batch is queued or none are left
@@ -197,7 +196,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
                 bool ok = false;
                 int b = 0, c = 0;
                 if (e < cend) {
-                    const int2 bc = A.bc[e];
+                    const int2 bc = Sy.bc[e];
                     b = bc.x;
                     c = bc.y;
                     ok = test(b, c);
@@ -210,7 +209,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
                     const long e = cur + lane;
                     nb = nc = ob = oc = 0;
                     if (e < cend) {
-                        const int2 bc = A.bc[e];
+                        const int2 bc = Sy.bc[e];
                         ob = Bs.leaf_lofs[bc.x * 4 + LB];
                         nb = Bs.leaf_lofs[bc.x * 4 + LB + 1] - ob;
                         oc = Bs.leaf_lofs[bc.y * 4 + LC];
@@ -252,7 +251,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
         fx_wave_sync();
     }
     // deterministic reduction of the 64 lane partials, then one write per element
-    const long rowbase = (long)Bs.f0[a] * A.n + Bs.f0[d];
+    const long rowbase = (long)Bs.f0[a] * Sy.n + Bs.f0[d];
     double outv = 0.0;
     if (COOP) {
         // lane t already owns element t of the block
@@ -264,7 +263,8 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
             if (lane == i) outv = s * (fx_comp_factor(LA, i / ND) * fx_comp_factor(LD, i % ND));
         }
     }
-    if (lane < NA * ND) A.kslot[rowbase + (long)(lane / ND) * A.n + (lane % ND)] = outv;
+    double* kslot = Sy.slots + (long)A.slot_index * Sy.n * Sy.n;
+    if (lane < NA * ND) kslot[rowbase + (long)(lane / ND) * Sy.n + (lane % ND)] = outv;
     if (A.times && lane == 0) A.times[u] = (float)(wall_clock64() - t_start);
     if (A.counters) {
         long np = npq;
@@ -275,6 +275,21 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
             atomicAdd(A.counters + 1, (unsigned long long)np);
         }
     }
+}
+
+// Kernel-level unit loop: one unit per wave, with an optional XCD-aware remap
+// of workgroups (fx_xcd_remap) so that neighbouring units -- which share
+// density and pair data -- run on one XCD and its L2.  K does not depend on
+// the mapping.
+template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, typename Fn>
+__device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
+    __shared__ int2 queue[WAVES][128];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    long blk = blockIdx.x;
+    if (A.flags & FX_LAUNCH_XCD) blk = fx_xcd_remap(blk, gridDim.x);
+    const long slot_unit = blk * WAVES + wave;
+    if (slot_unit >= A.nunits) return;
+    fx_class_unit<LA, LB, LC, LD, COOP, WAVES>(A, fn, slot_unit, wave, queue);
 }
 
 // Thread variant: one quartet per lane.
@@ -300,10 +315,12 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
     }
 
 #define FX_LAUNCH_THREAD(cls, prec)                                                                     \
-    hipLaunchKernelGGL(fx_k_##cls##_##prec, dim3((A.nunits + FX_CLASS_WAVES - 1) / FX_CLASS_WAVES),      \
+    hipLaunchKernelGGL(fx_k_##cls##_##prec,                                                             \
+                       dim3(grid > 0 ? grid : (A.nunits + FX_CLASS_WAVES - 1) / FX_CLASS_WAVES),         \
                        dim3(64 * FX_CLASS_WAVES), 0, st, A)
 #define FX_LAUNCH_COOP(cls, prec)                                                                       \
-    hipLaunchKernelGGL(fx_kc_##cls##_##prec, dim3((A.nunits + FX_COOP_WAVES - 1) / FX_COOP_WAVES),      \
+    hipLaunchKernelGGL(fx_kc_##cls##_##prec,                                                            \
+                       dim3(grid > 0 ? grid : (A.nunits + FX_COOP_WAVES - 1) / FX_COOP_WAVES),           \
                        dim3(64 * FX_COOP_WAVES), 0, st, A)
 
 // Both variants; `variant` 0 = thread, 1 = cooperative.
@@ -312,7 +329,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
     FX_THREAD_KERNEL(la, lb, lc, ld, cls, f32)                                                          \
     FX_COOP_KERNEL(la, lb, lc, ld, cls, f64, double)                                                    \
     FX_COOP_KERNEL(la, lb, lc, ld, cls, f32, float)                                                     \
-    int fx_launch_##cls(int prec32, int variant, FxClassArgs A, hipStream_t st) {                        \
+    int fx_launch_##cls(int prec32, int variant, FxClassArgs A, int grid, hipStream_t st) {              \
         if (variant == 1) {                                                                              \
             if (prec32) FX_LAUNCH_COOP(cls, f32); else FX_LAUNCH_COOP(cls, f64);                         \
             return 1;                                                                                    \
@@ -324,7 +341,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
 #define FX_DEFINE_CLASS_KERNELS_THREAD(la, lb, lc, ld, cls)                                             \
     FX_THREAD_KERNEL(la, lb, lc, ld, cls, f64)                                                          \
     FX_THREAD_KERNEL(la, lb, lc, ld, cls, f32)                                                          \
-    int fx_launch_##cls(int prec32, int, FxClassArgs A, hipStream_t st) {                                \
+    int fx_launch_##cls(int prec32, int, FxClassArgs A, int grid, hipStream_t st) {                      \
         if (prec32) FX_LAUNCH_THREAD(cls, f32); else FX_LAUNCH_THREAD(cls, f64);                         \
         return 0;                                                                                        \
     }
@@ -332,7 +349,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
 #define FX_DEFINE_CLASS_KERNELS_COOP(la, lb, lc, ld, cls)                                               \
     FX_COOP_KERNEL(la, lb, lc, ld, cls, f64, double)                                                    \
     FX_COOP_KERNEL(la, lb, lc, ld, cls, f32, float)                                                     \
-    int fx_launch_##cls(int prec32, int, FxClassArgs A, hipStream_t st) {                                \
+    int fx_launch_##cls(int prec32, int, FxClassArgs A, int grid, hipStream_t st) {                      \
         if (prec32) FX_LAUNCH_COOP(cls, f32); else FX_LAUNCH_COOP(cls, f64);                             \
         return 1;                                                                                        \
     }

@@ -501,13 +501,18 @@ static void build_tree(const fx_shells* s, const fx_tree_opts* opts, hipStream_t
 }
 
 // ---------------------------------------------------------------------------
-// kernel variant per class and precision (0 thread-per-quartet, 1 wave-per-
-// quartet); the thread form is the default, the autotuner may switch
+// per class and precision: kernel variant (0 thread-per-quartet, 1 wave-per-
+// quartet) and launch flags (FX_LAUNCH_*); thread form, no flags by default,
+// the autotuner may switch
 // ---------------------------------------------------------------------------
 static int g_variant[81][2];
+static int g_flags[81][2];
 static bool g_variant_init = [] {
     for (int c = 0; c < 81; ++c)
-        for (int p = 0; p < 2; ++p) g_variant[c][p] = (fx_class_variants[c] & 1) ? 0 : 1;
+        for (int p = 0; p < 2; ++p) {
+            g_variant[c][p] = (fx_class_variants[c] & 1) ? 0 : 1;
+            g_flags[c][p] = 0;
+        }
     return true;
 }();
 
@@ -524,9 +529,27 @@ struct Frontier {
     int p_base;
 };
 
+// one system of a call: tree, density, output and its per-call arrays
+struct SysCtx {
+    const fx_tree* T = nullptr;
+    const double* P = nullptr;
+    double* K = nullptr;
+    double* Pn = nullptr;
+    std::vector<double*> Psq;
+    double* slots = nullptr;
+};
+
+// a leaf-level traversal chunk, ready for the class launches
+struct LeafSeg {
+    std::unique_ptr<DevArena> arena;
+    FxSys sys{};
+    const fx_tree* T = nullptr;
+    int* units = nullptr;
+    long bounds[10] = {0};
+    long nitems = 0;
+};
+
 struct ExCtx {
-    const fx_tree* T;
-    const double* P;
     double tau;
     hipStream_t st;
     int precision;
@@ -534,11 +557,12 @@ struct ExCtx {
     int schedule;
     const fx_costmodel* cm;
     long cap;
-    std::vector<double*> Psq;
-    double* Pn;
-    double* slots;
+    int L;                          // slot layout: (highest l + 1)^2 (x2 in mixed mode)
     int nslot;
-    unsigned long long* counters;   // [2][81][2]: quartets, primitive quartets per class and precision
+    bool collect = false;           // batched: keep leaf segments for one launch per class
+    bool use_graph = false;
+    std::vector<std::unique_ptr<LeafSeg>> segs;
+    unsigned long long* counters;   // [81][2][2]: quartets, primitive quartets per class and precision
     fx_stats* stats;
     long* scan_partial;
     long scan_partial_cap;
@@ -557,8 +581,7 @@ struct ExCtx {
 static thread_local fx_task_timings* g_recording = nullptr;
 
 static int slot_index(const ExCtx& c, int lb, int lc, int prec32) {
-    const int L = c.T->lmax + 1;
-    return (lb * L + lc) * (c.precision == FX_PREC_MIXED ? 2 : 1) + prec32;
+    return (lb * c.L + lc) * (c.precision == FX_PREC_MIXED ? 2 : 1) + prec32;
 }
 
 static long* scan_partial(ExCtx& c, DevArena& A, long n) {
@@ -567,51 +590,102 @@ static long* scan_partial(ExCtx& c, DevArena& A, long n) {
     return c.scan_partial;
 }
 
-static void leaf_work(ExCtx& c, const Frontier& f) {
-    const fx_tree* T = c.T;
+// Units (K blocks) of a leaf chunk and, for single-shell leaves, its entries
+// grouped by density-side class.  In collect mode the chunk's entries are
+// copied so that the segment outlives the traversal.
+static std::unique_ptr<LeafSeg> prepare_seg(ExCtx& c, SysCtx& sc, const Frontier& f) {
+    const fx_tree* T = sc.T;
     hipStream_t st = c.st;
-    DevArena A(st);
+    auto seg = std::make_unique<LeafSeg>();
+    seg->arena = std::make_unique<DevArena>(st);
+    DevArena& A = *seg->arena;
+    seg->T = T;
     const long nitems = f.nad;
-    if (nitems == 0) return;
+    seg->nitems = nitems;
+    if (f.e_begin != 0) fx_fail(FX_ERR_INTERNAL, "leaf frontier does not start at entry 0");
     if (c.stats) c.stats->leaf_items += nitems;
     int* cnt = A.get<int>(9 * nitems);
     long* upos = A.get<long>(9 * nitems + 1);
     fx_launch_unit_count(f.ad, nitems, T->basis.leaf_lofs, cnt, st);
     fx_scan_i32(cnt, 9 * nitems, upos, scan_partial(c, A, 9 * nitems), c.scan_total, st);
-    std::vector<long> bounds(10);
-    for (int k = 0; k < 9; ++k) FX_HIP(hipMemcpyAsync(&bounds[k], upos + (long)k * nitems, sizeof(long), hipMemcpyDeviceToHost, st));
-    FX_HIP(hipMemcpyAsync(&bounds[9], upos + 9 * nitems, sizeof(long), hipMemcpyDeviceToHost, st));
+    for (int k = 0; k < 9; ++k)
+        FX_HIP(hipMemcpyAsync(&seg->bounds[k], upos + (long)k * nitems, sizeof(long), hipMemcpyDeviceToHost, st));
+    FX_HIP(hipMemcpyAsync(&seg->bounds[9], upos + 9 * nitems, sizeof(long), hipMemcpyDeviceToHost, st));
     FX_HIP(hipStreamSynchronize(st));
-    const long nunits = bounds[9];
+    const long nunits = seg->bounds[9];
     if (c.stats) c.stats->units += nunits;
-    int* units = A.get<int>(3 * std::max(1L, nunits));
-    fx_launch_unit_write(f.ad, nitems, 0, T->basis.leaf_lofs, T->basis.leaf_lsh, upos, units, st);
-    FX_HIP(hipGetLastError());
-
-    FxClassArgs args{};
-    args.basis = T->basis;
-    args.boys = T->boys;
-    args.P = c.P;
-    args.n = T->n;
-    args.Pn = c.Pn;
-    args.bc_off = f.bc_off;
-    args.bc = f.bc;
-    args.cls_off = nullptr;
+    seg->units = A.get<int>(3 * std::max(1L, nunits));
+    fx_launch_unit_write(f.ad, nitems, 0, T->basis.leaf_lofs, T->basis.leaf_lsh, upos, seg->units, st);
+    A.release(cnt);
+    A.release(upos);
+    FxSys& Y = seg->sys;
+    Y.basis = T->basis;
+    Y.P = sc.P;
+    Y.n = T->n;
+    Y.Pn = sc.Pn;
+    Y.bc_off = f.bc_off;
+    Y.bc = f.bc;
+    Y.cls_off = nullptr;
+    Y.slots = sc.slots;
+    const long ne = std::max(1L, f.e_count);
     if (T->single_shell_leaves) {
-        // leaf-level frontiers are always fresh arrays (chunking splits above the leaf level)
-        if (f.e_begin != 0) fx_fail(FX_ERR_INTERNAL, "leaf frontier does not start at entry 0");
-        const long ne = f.e_count;
-        int2* sorted = A.get<int2>(std::max(1L, ne));
+        int2* sorted = A.get<int2>(ne);
         long* cls_off = A.get<long>(10 * nitems);
         fx_launch_class_sort(f.bc_off, f.bc, nitems, T->basis.l, sorted, cls_off, st);
-        args.bc = sorted;
-        args.cls_off = cls_off;
+        Y.bc = sorted;
+        Y.cls_off = cls_off;
     }
-    args.tau = c.tau;
-    args.thr = c.thr;
-    const int Lm = T->lmax;
-    long maxlist = 0;
-    for (int k = 0; k < 9; ++k) maxlist = std::max(maxlist, bounds[k + 1] - bounds[k]);
+    if (c.collect) {
+        long* off = A.get<long>(nitems + 1);
+        FX_HIP(hipMemcpyAsync(off, f.bc_off, sizeof(long) * (nitems + 1), hipMemcpyDeviceToDevice, st));
+        Y.bc_off = off;
+        if (!T->single_shell_leaves) {
+            int2* bc = A.get<int2>(ne);
+            FX_HIP(hipMemcpyAsync(bc, f.bc, sizeof(int2) * f.e_count, hipMemcpyDeviceToDevice, st));
+            Y.bc = bc;
+        }
+    }
+    FX_HIP(hipGetLastError());
+    return seg;
+}
+
+// One launch per class and precision over the units of all segments.
+static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
+    hipStream_t st = c.st;
+    if (segs.empty()) return;
+    DevArena A(st);
+    const bool multi = segs.size() > 1;
+    int lmax = 0;
+    for (auto* g : segs) lmax = std::max(lmax, g->T->lmax);
+    // per (la, ld): merged unit lists
+    long total[9] = {0}, maxlist = 0;
+    for (int k = 0; k < 9; ++k) {
+        for (auto* g : segs) total[k] += g->bounds[k + 1] - g->bounds[k];
+        maxlist = std::max(maxlist, total[k]);
+    }
+    if (maxlist == 0) return;
+    int* munits[9] = {nullptr};
+    int* msys[9] = {nullptr};
+    FxSys* dsys = nullptr;
+    if (multi) {
+        std::vector<FxSys> hs;
+        for (auto* g : segs) hs.push_back(g->sys);
+        dsys = upload(A, hs);
+        for (int k = 0; k < 9; ++k) {
+            if (!total[k]) continue;
+            munits[k] = A.get<int>(3 * total[k]);
+            msys[k] = A.get<int>(total[k]);
+            long o = 0;
+            for (size_t j = 0; j < segs.size(); ++j) {
+                const long n = segs[j]->bounds[k + 1] - segs[j]->bounds[k];
+                if (!n) continue;
+                FX_HIP(hipMemcpyAsync(munits[k] + 3 * o, segs[j]->units + 3 * segs[j]->bounds[k], sizeof(int) * 3 * n,
+                                      hipMemcpyDeviceToDevice, st));
+                fx_launch_fill_i32(msys[k] + o, n, (int)j, st);
+                o += n;
+            }
+        }
+    }
     const bool sched = c.schedule != FX_SCHED_NONE;
     const bool use_mlp = c.schedule == FX_SCHED_MLP && c.cm;
     const int nbins = 32;
@@ -622,7 +696,8 @@ static void leaf_work(ExCtx& c, const Frontier& f) {
     long* bpos = nullptr;
     int* order = nullptr;
     float* times = nullptr;
-    if ((sched || c.rec) && maxlist > 0) {
+    long* bpartial = nullptr;
+    if (sched || c.rec) {
         feat = A.get<float4>(maxlist);
         cost = A.get<float>(maxlist);
         if (sched) {
@@ -630,30 +705,66 @@ static void leaf_work(ExCtx& c, const Frontier& f) {
             key = A.get<uint8_t>(maxlist);
             bpos = A.get<long>((size_t)nbins * maxlist + 1);
             order = A.get<int>(maxlist);
+            bpartial = A.get<long>(fx_scan_tiles((long)nbins * maxlist));
         }
         if (c.rec) times = A.get<float>(maxlist);
     }
-    long* bpartial = sched ? A.get<long>(fx_scan_tiles((long)nbins * std::max(1L, maxlist))) : nullptr;
+    const bool graph = c.use_graph && !c.profile && !c.rec;
+    hipGraph_t gr = nullptr;
+    // Capture on a library-owned stream (the caller's may be the legacy default
+    // stream, which cannot be captured); the graph is then launched on `st`.
+    hipStream_t launch_st = st;
+    struct CapStream {
+        hipStream_t s = nullptr;
+        ~CapStream() {
+            if (s) (void)hipStreamDestroy(s);
+        }
+    } cap;
+    if (graph) {
+        FX_HIP(hipStreamCreateWithFlags(&cap.s, hipStreamNonBlocking));
+        FX_HIP(hipStreamBeginCapture(cap.s, hipStreamCaptureModeThreadLocal));
+        st = cap.s;
+    }
     std::vector<float> hfeat, htime;
-    for (int la = 0; la <= Lm; ++la)
-        for (int ld = 0; ld <= Lm; ++ld) {
-            const int cls2 = la * 3 + ld;
-            const long u0 = bounds[cls2], u1 = bounds[cls2 + 1];
-            if (u1 <= u0) continue;
-            args.units = units + 3 * u0;
-            args.nunits = u1 - u0;
-            args.order = nullptr;
-            for (int lb = 0; lb <= Lm; ++lb)
-                for (int lc = 0; lc <= Lm; ++lc) {
+    FxClassArgs args{};
+    args.boys = segs[0]->T->boys;
+    args.tau = c.tau;
+    args.thr = c.thr;
+    const float* mean_np = segs[0]->T->mean_np;
+    for (int la = 0; la <= lmax; ++la)
+        for (int ld = 0; ld <= lmax; ++ld) {
+            const int k2 = la * 3 + ld;
+            if (!total[k2]) continue;
+            args.nunits = total[k2];
+            if (multi) {
+                args.units = munits[k2];
+                args.unit_sys = msys[k2];
+                args.sys = dsys;
+            } else {
+                args.units = segs[0]->units + 3 * segs[0]->bounds[k2];
+                args.unit_sys = nullptr;
+                args.sys = nullptr;
+                args.one = segs[0]->sys;
+            }
+            for (int lb = 0; lb <= lmax; ++lb)
+                for (int lc = 0; lc <= lmax; ++lc) {
                     const int cls = ((la * 3 + lb) * 3 + lc) * 3 + ld;
                     const int nprec = c.precision == FX_PREC_MIXED ? 2 : 1;
-                    const float class_cost = std::log2(
-                        (float)fx_class_vrr_flops[cls] * T->mean_np[lb] * T->mean_np[lc] + (float)fx_class_hrr_flops[cls] + 1.f);
+                    const float class_cost =
+                        std::log2((float)fx_class_vrr_flops[cls] * mean_np[lb] * mean_np[lc] +
+                                  (float)fx_class_hrr_flops[cls] + 1.f);
                     args.order = nullptr;
                     args.times = nullptr;
                     if (feat) {
-                        fx_launch_unit_features(args.units, args.nunits, f.bc_off, args.cls_off, lb * 3 + lc,
-                                                T->basis.nprim, T->qrow, class_cost, feat, st);
+                        long o = 0;
+                        for (auto* g : segs) {
+                            const long n = g->bounds[k2 + 1] - g->bounds[k2];
+                            if (n)
+                                fx_launch_unit_features(g->units + 3 * g->bounds[k2], n, g->sys.bc_off, g->sys.cls_off,
+                                                        lb * 3 + lc, g->T->basis.nprim, g->T->qrow, class_cost,
+                                                        feat + o, st);
+                            o += n;
+                        }
                     }
                     if (sched) {
                         // predicted log2 cost per unit: the learned model, or the
@@ -670,18 +781,20 @@ static void leaf_work(ExCtx& c, const Frontier& f) {
                         if (c.rec) args.times = times;
                         args.mode = c.precision == FX_PREC_MIXED ? (pr ? FX_MODE_MIXED_LO : FX_MODE_MIXED_HI)
                                                                  : FX_MODE_ALL;
-                        args.kslot = c.slots + (long)slot_index(c, lb, lc, pr) * T->n * T->n;
+                        args.slot_index = slot_index(c, lb, lc, pr);
                         args.counters = c.counters + (cls * 2 + pr) * 2;
+                        args.flags = g_flags[cls][pr];
+                        const int grid = 0;
                         if (c.profile) {
                             ExCtx::Timed t{cls * 2 + pr, nullptr, nullptr};
                             FX_HIP(hipEventCreate(&t.a));
                             FX_HIP(hipEventCreate(&t.b));
                             FX_HIP(hipEventRecord(t.a, st));
-                            fx_class_table[cls](pr, g_variant[cls][pr], args, st);
+                            fx_class_table[cls](pr, g_variant[cls][pr], args, grid, st);
                             FX_HIP(hipEventRecord(t.b, st));
                             c.timed.push_back(t);
                         } else {
-                            fx_class_table[cls](pr, g_variant[cls][pr], args, st);
+                            fx_class_table[cls](pr, g_variant[cls][pr], args, grid, st);
                         }
                         if (c.rec) {
                             const long n = args.nunits;
@@ -699,18 +812,39 @@ static void leaf_work(ExCtx& c, const Frontier& f) {
                     }
                 }
         }
+    if (graph) {
+        FX_HIP(hipStreamEndCapture(cap.s, &gr));
+        st = launch_st;
+        hipGraphExec_t ge = nullptr;
+        hipError_t e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphLaunch(ge, st);
+        if (ge) (void)hipGraphExecDestroy(ge);
+        (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) fx_fail(FX_ERR_HIP, std::string("class-launch graph: ") + hipGetErrorString(e));
+        if (c.stats) c.stats->graph_nodes += 1;
+    }
     FX_HIP(hipGetLastError());
     FX_HIP(hipStreamSynchronize(st));
 }
 
-static void traverse(ExCtx& c, int k, const Frontier& f) {
-    const fx_tree* T = c.T;
+static void leaf_work(ExCtx& c, SysCtx& sc, const Frontier& f) {
+    if (f.nad == 0) return;
+    auto seg = prepare_seg(c, sc, f);
+    if (c.collect) {
+        c.segs.push_back(std::move(seg));
+        return;
+    }
+    run_classes(c, {seg.get()});
+}
+
+static void traverse(ExCtx& c, SysCtx& sc, int k, const Frontier& f) {
+    const fx_tree* T = sc.T;
     hipStream_t st = c.st;
     const int nl = (int)T->levels.size();
     if (c.stats) c.stats->frontier[k] += f.e_count;
     if (k == nl - 1) {
         auto t0 = std::chrono::steady_clock::now();
-        leaf_work(c, f);
+        leaf_work(c, sc, f);
         c.seconds_eri += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         return;
     }
@@ -728,7 +862,7 @@ static void traverse(ExCtx& c, int k, const Frontier& f) {
     L.ch0 = T->d_ch0[k];
     L.nch = T->d_nch[k];
     L.Qsq = T->d_Qsq[k + 1];
-    L.Psq = c.Psq[k + 1];
+    L.Psq = sc.Psq[k + 1];
     L.nk1 = (int)T->levels[k + 1].sL.size();
     L.tau2 = c.tau * c.tau;
     const long nm = 4 * f.e_count;
@@ -757,8 +891,8 @@ static void traverse(ExCtx& c, int k, const Frontier& f) {
             c.stats->chunks += 1;
             c.stats->frontier[k] -= f.e_count;   // re-counted by the halves
         }
-        traverse(c, k, f1);
-        traverse(c, k, f2);
+        traverse(c, sc, k, f1);
+        traverse(c, sc, k, f2);
         return;
     }
     if (total > (1L << 31) - 1) fx_fail(FX_ERR_OOM, "a single K block pair exceeds the frontier capacity");
@@ -785,7 +919,7 @@ static void traverse(ExCtx& c, int k, const Frontier& f) {
     A.release(pos);
     A.release(flag);
     A.release(adpos);
-    traverse(c, k + 1, g);
+    traverse(c, sc, k + 1, g);
 }
 
 static void validate_exchange(const fx_tree* T, const double* P, double tau, const double* K) {
@@ -796,10 +930,7 @@ static void validate_exchange(const fx_tree* T, const double* P, double tau, con
     if (((uintptr_t)P & 7) || ((uintptr_t)K & 7)) fx_fail(FX_ERR_INVALID_ARG, "P and K must be 8-byte aligned");
 }
 
-static void exchange_impl(const fx_tree* T, const double* P, double tau, double* K, const fx_exchange_opts* opts,
-                          fx_stats* stats, hipStream_t st) {
-    auto t0 = std::chrono::steady_clock::now();
-    validate_exchange(T, P, tau, K);
+static fx_exchange_opts checked_opts(const fx_exchange_opts* opts) {
     fx_exchange_opts o{};
     o.precision = FX_PREC_FP64;
     o.fp32_threshold = 1e-5;
@@ -811,16 +942,21 @@ static void exchange_impl(const fx_tree* T, const double* P, double tau, double*
     if (o.schedule < 0 || o.schedule > 2) fx_fail(FX_ERR_INVALID_ARG, "bad schedule");
     if (!std::isfinite(o.alpha) || !std::isfinite(o.beta)) fx_fail(FX_ERR_INVALID_ARG, "alpha/beta not finite");
     if (o.precision == FX_PREC_MIXED && !(o.fp32_threshold >= 0.0)) fx_fail(FX_ERR_INVALID_ARG, "bad fp32_threshold");
-    if (stats) {
-        std::memset(stats, 0, sizeof(*stats));
-        stats->levels = (int)T->levels.size();
-    }
-    const int S = T->S;
-    const long n = T->n, nn = n * n;
+    return o;
+}
+
+// Exchange of one or several systems.  Several systems are traversed one
+// after another, their leaf segments kept, and every class kernel is then
+// launched once over the units of all systems.
+static void exchange_many(const fx_tree* const* trees, const double* const* Ps, double* const* Ks, int count,
+                          double tau, const fx_exchange_opts* opts, fx_stats* stats, hipStream_t st) {
+    auto t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < count; ++i) validate_exchange(trees[i], Ps[i], tau, Ks[i]);
+    const fx_exchange_opts o = checked_opts(opts);
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (count == 0) return;
     DevArena A(st);
     ExCtx c{};
-    c.T = T;
-    c.P = P;
     c.tau = tau;
     c.st = st;
     c.precision = o.precision;
@@ -830,6 +966,8 @@ static void exchange_impl(const fx_tree* T, const double* P, double tau, double*
     c.cap = o.max_frontier_entries > 0 ? o.max_frontier_entries : (1L << 30);
     c.stats = stats;
     c.profile = o.profile;
+    c.collect = count > 1;
+    c.use_graph = o.use_graph != 0;
     c.rec = g_recording;
     if (c.rec) {
         int dev = 0, khz = 0;
@@ -838,45 +976,70 @@ static void exchange_impl(const fx_tree* T, const double* P, double tau, double*
             c.tick_ns = 1e6 / (double)khz;
     }
     if (o.schedule == FX_SCHED_MLP && !o.costmodel) c.schedule = FX_SCHED_BOUND;
-    // density norms
-    c.Pn = A.get<double>((size_t)S * S);
-    fx_launch_pnorm(P, n, T->basis.l, T->basis.f0, S, c.Pn, st);
-    const int nl = (int)T->levels.size();
-    c.Psq.resize(nl);
-    for (int k = nl - 1; k >= 0; --k) {
-        const int nk = (int)T->levels[k].sL.size();
-        c.Psq[k] = A.get<double>((size_t)nk * nk);
-        if (k == nl - 1)
-            fx_launch_leaf_sq(c.Pn, S, T->d_sL[k], T->d_sR[k], nk, c.Psq[k], st);
-        else
-            fx_launch_level_up(c.Psq[k + 1], (int)T->levels[k + 1].sL.size(), T->d_ch0[k], T->d_nch[k], nk, c.Psq[k], st);
-    }
-    // slots
-    c.nslot = (T->lmax + 1) * (T->lmax + 1) * (o.precision == FX_PREC_MIXED ? 2 : 1);
-    c.slots = A.get<double>((size_t)c.nslot * nn);
-    fx_launch_fill(c.slots, (long)c.nslot * nn, 0.0, st);
+    int lmax = 0;
+    for (int i = 0; i < count; ++i) lmax = std::max(lmax, trees[i]->lmax);
+    c.L = lmax + 1;
+    c.nslot = c.L * c.L * (o.precision == FX_PREC_MIXED ? 2 : 1);
     c.counters = A.get<unsigned long long>(81 * 2 * 2);
     FX_HIP(hipMemsetAsync(c.counters, 0, sizeof(unsigned long long) * 81 * 4, st));
     c.scan_partial_cap = 1 << 16;
     c.scan_partial = A.get<long>(c.scan_partial_cap);
     c.scan_total = A.get<long>(1);
-    FX_HIP(hipGetLastError());
-    // root task
-    const double q0 = read1(T->d_Qsq[0], st), p0 = read1(c.Psq[0], st);
-    if ((q0 * q0) * p0 * (1.0 + 1e-12) > tau * tau) {
-        DevArena R(st);
-        Frontier f{};
-        f.ad = upload(R, std::vector<int2>{make_int2(0, 0)});
-        f.bc_off = upload(R, std::vector<long>{0, 1});
-        f.bc = upload(R, std::vector<int2>{make_int2(0, 0)});
-        f.parent = upload(R, std::vector<int>{0});
-        f.nad = 1;
-        f.e_begin = 0;
-        f.e_count = 1;
-        f.p_base = 0;
-        traverse(c, 0, f);
+    std::vector<SysCtx> sys(count);
+    for (int i = 0; i < count; ++i) {
+        SysCtx& sc = sys[i];
+        const fx_tree* T = trees[i];
+        sc.T = T;
+        sc.P = Ps[i];
+        sc.K = Ks[i];
+        const int S = T->S;
+        const long n = T->n, nn = n * n;
+        if (stats) stats->levels = std::max(stats->levels, (int)T->levels.size());
+        // density norms
+        sc.Pn = A.get<double>((size_t)S * S);
+        fx_launch_pnorm(sc.P, n, T->basis.l, T->basis.f0, S, sc.Pn, st);
+        const int nl = (int)T->levels.size();
+        sc.Psq.resize(nl);
+        for (int k = nl - 1; k >= 0; --k) {
+            const int nk = (int)T->levels[k].sL.size();
+            sc.Psq[k] = A.get<double>((size_t)nk * nk);
+            if (k == nl - 1)
+                fx_launch_leaf_sq(sc.Pn, S, T->d_sL[k], T->d_sR[k], nk, sc.Psq[k], st);
+            else
+                fx_launch_level_up(sc.Psq[k + 1], (int)T->levels[k + 1].sL.size(), T->d_ch0[k], T->d_nch[k], nk,
+                                   sc.Psq[k], st);
+        }
+        sc.slots = A.get<double>((size_t)c.nslot * nn);
+        fx_launch_fill(sc.slots, (long)c.nslot * nn, 0.0, st);
+        FX_HIP(hipGetLastError());
+        // root task
+        const double q0 = read1(T->d_Qsq[0], st), p0 = read1(sc.Psq[0], st);
+        if ((q0 * q0) * p0 * (1.0 + 1e-12) > tau * tau) {
+            DevArena R(st);
+            Frontier f{};
+            f.ad = upload(R, std::vector<int2>{make_int2(0, 0)});
+            f.bc_off = upload(R, std::vector<long>{0, 1});
+            f.bc = upload(R, std::vector<int2>{make_int2(0, 0)});
+            f.parent = upload(R, std::vector<int>{0});
+            f.nad = 1;
+            f.e_begin = 0;
+            f.e_count = 1;
+            f.p_base = 0;
+            traverse(c, sc, 0, f);
+        }
     }
-    fx_launch_finalize(c.slots, c.nslot, nn, o.alpha, o.beta, K, st);
+    if (c.collect) {
+        auto t1 = std::chrono::steady_clock::now();
+        std::vector<LeafSeg*> segs;
+        for (auto& g : c.segs) segs.push_back(g.get());
+        run_classes(c, segs);
+        c.segs.clear();
+        c.seconds_eri += std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
+    }
+    for (int i = 0; i < count; ++i) {
+        const long nn = (long)sys[i].T->n * sys[i].T->n;
+        fx_launch_finalize(sys[i].slots, c.nslot, nn, o.alpha, o.beta, sys[i].K, st);
+    }
     FX_HIP(hipGetLastError());
     struct EvGuard {
         ExCtx& c;
@@ -915,6 +1078,11 @@ static void exchange_impl(const fx_tree* T, const double* P, double tau, double*
     }
 }
 
+static void exchange_impl(const fx_tree* T, const double* P, double tau, double* K, const fx_exchange_opts* opts,
+                          fx_stats* stats, hipStream_t st) {
+    exchange_many(&T, &P, &K, 1, tau, opts, stats, st);
+}
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -948,27 +1116,7 @@ fx_status fx_exchange_batched(const fx_tree* const* trees, const double* const* 
                               double tau, const fx_exchange_opts* opts, fx_stats* stats, void* stream) {
     return fx_guard([&] {
         if (count < 0 || (count > 0 && (!trees || !P || !K))) fx_fail(FX_ERR_INVALID_ARG, "bad batch arrays");
-        for (int i = 0; i < count; ++i) validate_exchange(trees[i], P[i], tau, K[i]);
-        fx_stats acc{}, one{};
-        for (int i = 0; i < count; ++i) {
-            exchange_impl(trees[i], P[i], tau, K[i], opts, stats ? &one : nullptr, (hipStream_t)stream);
-            if (stats) {
-                acc.levels = std::max(acc.levels, one.levels);
-                for (int k = 0; k < FX_STATS_MAX_LEVELS; ++k) acc.frontier[k] += one.frontier[k];
-                acc.leaf_items += one.leaf_items;
-                acc.units += one.units;
-                acc.quartets += one.quartets;
-                acc.quartets_fp32 += one.quartets_fp32;
-                for (int k = 0; k < 81; ++k) acc.class_quartets[k] += one.class_quartets[k];
-                acc.prim_quartets += one.prim_quartets;
-                acc.flops += one.flops;
-                acc.chunks += one.chunks;
-                acc.seconds_traversal += one.seconds_traversal;
-                acc.seconds_eri += one.seconds_eri;
-                acc.seconds_total += one.seconds_total;
-            }
-        }
-        if (stats) *stats = acc;
+        exchange_many(trees, P, K, count, tau, opts, stats, (hipStream_t)stream);
     });
 }
 
@@ -1032,6 +1180,20 @@ fx_status fx_set_class_variant(int32_t cls, int32_t prec32, int32_t variant) {
         if (!(fx_class_variants[cls] & (1 << variant))) fx_fail(FX_ERR_UNSUPPORTED, "variant not built for this class");
         g_variant[cls][prec32] = variant;
     });
+}
+
+fx_status fx_set_class_launch(int32_t cls, int32_t prec32, int32_t flags) {
+    return fx_guard([&] {
+        if (cls < 0 || cls >= 81 || prec32 < 0 || prec32 > 1 || flags < 0 || flags > 3)
+            fx_fail(FX_ERR_INVALID_ARG, "class 0..80, prec32 0..1, flags 0..3");
+        if (flags & 2) fx_fail(FX_ERR_UNSUPPORTED, "persistent class launches are switched off");
+        g_flags[cls][prec32] = flags;
+    });
+}
+
+int32_t fx_get_class_launch(int32_t cls, int32_t prec32) {
+    if (cls < 0 || cls >= 81 || prec32 < 0 || prec32 > 1) return -1;
+    return g_flags[cls][prec32];
 }
 
 int32_t fx_get_class_variant(int32_t cls, int32_t prec32) {
@@ -1255,6 +1417,8 @@ fx_status fx_costmodel_train(const fx_task_timings* data, const fx_train_opts* o
         *out = guard.release();
     });
 }
+
+int64_t fx_xcd_block(int64_t b, int64_t nb) { return (b < 0 || b >= nb) ? -1 : fx_xcd_remap(b, nb); }
 
 // Host-only planning (no device work): the tree order and the bisection
 // levels.  perm[nshell]; nodes: 4 ints per node (level, first shell, end

@@ -41,29 +41,50 @@ struct FxDevBasis {
     const FxPrimPair* pp; // [Nt*Nt] primitive-pair records, (global prim i, global prim j)
 };
 
-// Arguments of one class kernel launch.
-struct FxClassArgs {
+// One system (or traversal chunk) as seen by the class kernels.
+struct FxSys {
     FxDevBasis basis;
-    const double* boys;
     const double* P;
     long n;
     const double* Pn;                 // [S*S] shell-level ||P_bc||_F
-    const int* units;                 // [3*nunits] (item, a, d)
-    const int* order;                 // schedule permutation of units, or null
-    long nunits;
     const long* bc_off;               // per leaf item: offsets into bc
     const int2* bc;                   // (B, C) leaf nodes
     const long* cls_off;              // single-shell leaves: per item 10 class offsets, else null
+    double* slots;                    // K slots of this system, n*n each
+};
+
+// launch options (autotuned per class and precision)
+#define FX_LAUNCH_XCD 1               // XCD-aware workgroup remap
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b % 8).  This bijection of [0, nb) gives XCD x the logical blocks
+// [x*q + min(x, r), ...) of a contiguous range (q = nb / 8, r = nb % 8), so
+// consecutive logical blocks share an XCD and its L2.
+__host__ __device__ inline long fx_xcd_remap(long b, long nb) {
+    const long q = nb / 8, r = nb % 8, x = b % 8, i = b / 8;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// Arguments of one class kernel launch.
+struct FxClassArgs {
+    FxSys one;                        // the system when sys == null
+    const FxSys* sys;                 // batched launches: per-unit system descriptors
+    const int* unit_sys;              // batched launches: system of every unit
+    const double* boys;
+    const int* units;                 // [3*nunits] (item, a, d)
+    const int* order;                 // schedule permutation of units, or null
+    long nunits;
+    int slot_index;                   // K slot of this (lb, lc, precision)
     double tau, thr;
     int mode;                         // FX_MODE_*
-    double* kslot;                    // n*n slot for this (lb, lc, precision)
+    int flags;                        // FX_LAUNCH_*
     unsigned long long* counters;     // computed quartets (nullable)
     float* times;                     // per-unit wall-clock ticks (nullable; timing probes)
 };
 
-// Launchers defined in the generated class files.
-// returns the variant launched (0 thread, 1 cooperative)
-#define FX_DECLARE_LAUNCH(cls) int fx_launch_##cls(int prec32, int variant, FxClassArgs A, hipStream_t st);
-typedef int (*fx_class_launcher)(int, int, FxClassArgs, hipStream_t);
+// returns the variant launched (0 thread, 1 cooperative); `grid` workgroups
+// for persistent launches, 0 = one wave per unit
+#define FX_DECLARE_LAUNCH(cls) int fx_launch_##cls(int prec32, int variant, FxClassArgs A, int grid, hipStream_t st);
+typedef int (*fx_class_launcher)(int, int, FxClassArgs, int, hipStream_t);
 void fx_launch_schwarz(FxDevBasis B, const double* boys, const int2* pairs, long npairs, double* Qn,
                        hipStream_t st);

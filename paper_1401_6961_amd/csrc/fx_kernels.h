@@ -42,4 +42,6 @@ void fx_launch_unit_write(const int2* items, long nitems, long item_base, const 
 void fx_launch_class_sort(const long* bc_off, const int2* bc, long nitems, const int* l, int2* out, long* cls_off,
                           hipStream_t st);
 void fx_launch_fill(double* x, long n, double v, hipStream_t st);
+void fx_launch_fill_i32(int* x, long n, int v, hipStream_t st);
+void fx_launch_fill_u32(unsigned int* x, long n, unsigned int v, hipStream_t st);
 void fx_launch_finalize(const double* slots, int nslot, long nn, double alpha, double beta, double* K, hipStream_t st);

@@ -459,6 +459,27 @@ __global__ void fx_k_fill(double* __restrict__ x, long n, double v) {
     for (long k = i; k < n; k += stride) x[k] = v;
 }
 
+template <typename T>
+__global__ void fx_k_fill_t(T* __restrict__ x, long n, T v) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long k = i; k < n; k += stride) x[k] = v;
+}
+
+void fx_launch_fill_i32(int* x, long n, int v, hipStream_t st) {
+    if (n <= 0) return;
+    long blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fx_k_fill_t<int>, dim3(blocks), dim3(256), 0, st, x, n, v);
+}
+
+void fx_launch_fill_u32(unsigned int* x, long n, unsigned int v, hipStream_t st) {
+    if (n <= 0) return;
+    long blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fx_k_fill_t<unsigned int>, dim3(blocks), dim3(256), 0, st, x, n, v);
+}
+
 void fx_launch_fill(double* x, long n, double v, hipStream_t st) {
     if (n <= 0) return;
     long blocks = (n + 255) / 256;

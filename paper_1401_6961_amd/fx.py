@@ -39,7 +39,8 @@ class fx_exchange_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("fp32_threshold", ctypes.c_double),
                 ("schedule", ctypes.c_int32), ("costmodel", ctypes.c_void_p),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
-                ("max_frontier_entries", ctypes.c_int64), ("profile", ctypes.c_int32)]
+                ("max_frontier_entries", ctypes.c_int64), ("profile", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
 
 
 class fx_train_opts(ctypes.Structure):
@@ -52,7 +53,7 @@ class fx_stats(ctypes.Structure):
                 ("leaf_items", ctypes.c_int64), ("units", ctypes.c_int64),
                 ("quartets", ctypes.c_int64), ("quartets_fp32", ctypes.c_int64),
                 ("class_quartets", ctypes.c_int64 * 81), ("prim_quartets", ctypes.c_double),
-                ("flops", ctypes.c_double), ("chunks", ctypes.c_int32),
+                ("flops", ctypes.c_double), ("chunks", ctypes.c_int32), ("graph_nodes", ctypes.c_int32),
                 ("class_seconds", ctypes.c_double * 162), ("class_launches", ctypes.c_int32 * 162),
                 ("class_flops", ctypes.c_double * 162), ("class_prec_quartets", ctypes.c_int64 * 162),
                 ("seconds_traversal", ctypes.c_double), ("seconds_eri", ctypes.c_double),
@@ -64,6 +65,7 @@ class fx_stats(ctypes.Structure):
                 "quartets_fp32": self.quartets_fp32,
                 "class_quartets": np.array(self.class_quartets, dtype=np.int64).reshape(3, 3, 3, 3),
                 "prim_quartets": self.prim_quartets, "flops": self.flops, "chunks": self.chunks,
+                "graph_nodes": self.graph_nodes,
                 "seconds_traversal": self.seconds_traversal, "seconds_eri": self.seconds_eri,
                 "seconds_total": self.seconds_total,
                 "class_seconds": np.array(self.class_seconds).reshape(81, 2),
@@ -76,6 +78,7 @@ EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_b
             "fx_tree_perm", "fx_tree_levels", "fx_tree_schwarz", "fx_tree_free", "fx_set_allocator",
             "fx_status_string", "fx_last_error_message", "fx_plan_tree", "fx_hilbert_key3",
             "fx_set_class_variant", "fx_get_class_variant", "fx_class_variants_available",
+            "fx_set_class_launch", "fx_get_class_launch", "fx_xcd_block",
             "fx_record_task_timings", "fx_task_timings_create", "fx_task_timings_count", "fx_task_timings_get",
             "fx_task_timings_free", "fx_costmodel_train", "fx_costmodel_nparams", "fx_costmodel_create",
             "fx_costmodel_params", "fx_costmodel_predict", "fx_costmodel_loss_grad", "fx_costmodel_free"]
@@ -122,6 +125,12 @@ def lib():
     L.fx_get_class_variant.restype = i32
     L.fx_class_variants_available.argtypes = [i32]
     L.fx_class_variants_available.restype = i32
+    L.fx_set_class_launch.argtypes = [i32, i32, i32]
+    L.fx_set_class_launch.restype = ctypes.c_int
+    L.fx_get_class_launch.argtypes = [i32, i32]
+    L.fx_get_class_launch.restype = i32
+    L.fx_xcd_block.argtypes = [i64, i64]
+    L.fx_xcd_block.restype = i64
     fp = ctypes.POINTER(ctypes.c_float)
     L.fx_record_task_timings.argtypes = [vp, vp, dbl, ctypes.POINTER(fx_exchange_opts), ctypes.POINTER(vp), vp]
     L.fx_task_timings_create.argtypes = [fp, fp, ctypes.POINTER(i32), i64, ctypes.POINTER(vp)]
@@ -246,10 +255,11 @@ def build_quadtree_from(system, **kw) -> Tree:
 
 
 def make_opts(precision=FX_PREC_FP64, fp32_threshold=1e-5, schedule=FX_SCHED_BOUND, costmodel=None, alpha=1.0,
-              beta=0.0, max_frontier_entries=0, profile=False):
+              beta=0.0, max_frontier_entries=0, profile=False, use_graph=False):
     return fx_exchange_opts(int(precision), float(fp32_threshold), int(schedule),
                             ctypes.c_void_p(costmodel.handle if costmodel is not None else None),
-                            float(alpha), float(beta), int(max_frontier_entries), int(bool(profile)))
+                            float(alpha), float(beta), int(max_frontier_entries), int(bool(profile)),
+                            int(bool(use_graph)))
 
 
 def fx_exchange(tree: Tree, P, tau, K, stream=None):
@@ -433,3 +443,11 @@ def fx_costmodel_train(timings, steps=2000, batch=8192, lr=3e-3, seed=12345, str
     _check(lib().fx_costmodel_train(timings.handle, ctypes.byref(o), ctypes.byref(h), ctypes.byref(loss),
                                     _stream_ptr(stream)))
     return CostModel(h.value), float(loss.value)
+
+
+def fx_set_class_launch(cls, prec32, flags):
+    _check(lib().fx_set_class_launch(int(cls), int(prec32), int(flags)))
+
+
+def fx_get_class_launch(cls, prec32):
+    return int(lib().fx_get_class_launch(int(cls), int(prec32)))

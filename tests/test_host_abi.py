@@ -139,3 +139,19 @@ def test_hilbert_order_keeps_atoms_together():
         pos = np.nonzero(atoms == a)[0]
         assert np.all(np.diff(pos) == 1)
         assert list(s.l[perm][pos]) == [0, 1, 2]
+
+
+def test_xcd_remap_is_a_bijection():
+    L = fx.lib()
+    for nb in list(range(1, 70)) + [255, 256, 1000, 4099]:
+        img = [L.fx_xcd_block(b, nb) for b in range(nb)]
+        assert sorted(img) == list(range(nb))
+        # consecutive logical blocks of one XCD: b and b + 8 map to neighbours
+        for b in range(nb - 8):
+            assert img[b + 8] == img[b] + 1
+    assert L.fx_xcd_block(5, 5) == -1
+
+
+def test_persistent_launch_flag_is_switched_off():
+    with pytest.raises(fx.FxError):
+        fx.fx_set_class_launch(0, 0, 2)
