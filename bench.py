@@ -65,6 +65,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison build")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", default="cluster", choices=["cluster", "batched", "slab-mlp"],
+                    help="cluster: the headline 1000-atom s+p+d build; batched: 64 clusters in one batched "
+                         "call vs 64 sequential builds; slab-mlp: 4000-atom s+p slab, learned vs bound-only "
+                         "scheduling")
+    ap.add_argument("--no-tuning", action="store_true", help="ignore the autotuned kernel table")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -73,9 +78,17 @@ def main():
     import torch
     import synthetic
     import paper_1401_6961_amd as fx
+    from paper_1401_6961_amd import autotune
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
+
+    tuned = 0 if args.no_tuning else autotune.apply()
+    log(f"bench: {tuned} autotuned class entries applied")
+    if args.workload == "batched":
+        return bench_batched(args, log)
+    if args.workload == "slab-mlp":
+        return bench_slab_mlp(args, log)
 
     log(f"bench: generating {args.natom}-atom s+p+d cluster")
     system = synthetic.cluster(args.natom)
@@ -121,6 +134,17 @@ def main():
                 "flops_per_launch": per_launch_flops,
                 "all_class_kernels_tflops": float(cf.sum() / cs.sum() / 1e12) if cs.sum() > 0 else None}
 
+    order = np.argsort(-cs.reshape(-1))[:12]
+    top = []
+    for idx in order:
+        cc, pp = divmod(int(idx), 2)
+        if cs[cc, pp] <= 0:
+            continue
+        top.append({"class": cname(cc), "prec": "f32" if pp else "f64", "s": float(cs[cc, pp]),
+                    "tflops": float(cf[cc, pp] / cs[cc, pp] / 1e12),
+                    "quartets": int(sum(s_["class_prec_quartets"][cc, pp] for s_ in stats))})
+    roofline["top_class_kernels"] = top
+
     extra = {}
     if not args.no_fp64:
         log("bench: FP64 comparison build")
@@ -151,9 +175,96 @@ def main():
            "kbuild_s": elapsed / args.steps, "quartets": int(quartets), "quartets_fp32": int(st["quartets_fp32"]),
            "prim_quartets": st["prim_quartets"], "alg_flops": st["flops"],
            "alg_tflops": st["flops"] / (elapsed / args.steps) / 1e12, "tree_build_s": t_tree,
-           "traversal_s": st["seconds_traversal"], "roofline": roofline, "cpu_baseline": cpu}
+           "traversal_s": st["seconds_traversal"], "autotuned_entries": tuned, "roofline": roofline,
+           "cpu_baseline": cpu}
     out.update(extra)
     print(json.dumps(out))
+
+
+def bench_batched(args, log):
+    """64 clusters (50..500 atoms, s+p) in one batched, graph-captured call vs
+    64 sequential single builds (same precision, same K bitwise)."""
+    import torch
+    import synthetic
+    import paper_1401_6961_amd as fx
+    systems = synthetic.batch_clusters(64)
+    trees = [fx.build_quadtree_from(s) for s in systems]
+    Ps = [torch.from_numpy(s.P).cuda() for s in systems]
+    tau = systems[0].tau
+    opts = fx.make_opts(precision=fx.FX_PREC_MIXED, use_graph=True)
+    Kb = [torch.zeros_like(P) for P in Ps]
+    for _ in range(args.warmup):
+        fx.fx_exchange_batched(trees, Ps, Kb, tau, opts)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        Kb, st = fx.fx_exchange_batched(trees, Ps, Kb, tau, opts)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t) / args.steps
+    log("bench: 64 sequential builds")
+    Ks = [torch.zeros_like(P) for P in Ps]
+    t = time.perf_counter()
+    q = 0
+    for tr, P, K in zip(trees, Ps, Ks):
+        _, s1 = fx.fx_exchange_ex(tr, P, tau, K, fx.make_opts(precision=fx.FX_PREC_MIXED))
+        q += s1["quartets"]
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t
+    same = all(torch.equal(a, b_) for a, b_ in zip(Kb, Ks))
+    print(json.dumps({"metric": "batched K-build s, 64 clusters 50-500 atoms s+p, tau=1e-8, mixed",
+                      "value": st["quartets"] / tb, "unit": "quartets/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": 1e3 * tb, "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+                      "config": {"workload": "64 s+p clusters, log-uniform 50..500 atoms, one batched graph-captured call",
+                                 "systems": 64, "nbf_total": int(sum(s.nbf for s in systems))},
+                      "batched_s": tb, "sequential_s": ts, "speedup": ts / tb, "quartets": st["quartets"],
+                      "sequential_quartets": q, "K_bitwise_equal": bool(same)}))
+
+
+def bench_slab_mlp(args, log):
+    """4000-atom s+p slab: learned (MLP) vs bound-only scheduling, same K."""
+    import numpy as np
+    import torch
+    import synthetic
+    import paper_1401_6961_amd as fx
+    log("bench: recording unit timings on smaller systems for training")
+    recs = []
+    for s in (synthetic.chain(200), synthetic.cluster(300, seed=1002), synthetic.cluster(400, seed=7, with_d=False)):
+        tr = fx.build_quadtree_from(s)
+        rec = fx.fx_record_task_timings(tr, torch.from_numpy(s.P).cuda(), s.tau,
+                                        fx.make_opts(precision=fx.FX_PREC_MIXED))
+        recs.append(rec.arrays())
+    f = np.concatenate([r[0] for r in recs])
+    t = np.concatenate([r[1] for r in recs])
+    data = fx.TaskTimings.from_arrays(f, t)
+    model, loss = fx.fx_costmodel_train(data, steps=2000, batch=8192)
+    log(f"bench: trained on {len(t)} samples, loss {loss:.3f}")
+    s = synthetic.slab(args.natom if args.natom != 1000 else 4000)
+    tree = fx.build_quadtree_from(s)
+    P = torch.from_numpy(s.P).cuda()
+    res = {}
+    Ks = {}
+    for name, sched, cm in (("bound", fx.FX_SCHED_BOUND, None), ("mlp", fx.FX_SCHED_MLP, model)):
+        K = torch.zeros_like(P)
+        opts = fx.make_opts(precision=fx.FX_PREC_MIXED, schedule=sched, costmodel=cm)
+        for _ in range(args.warmup):
+            fx.fx_exchange_ex(tree, P, s.tau, K, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, st = fx.fx_exchange_ex(tree, P, s.tau, K, opts)
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / args.steps
+        Ks[name] = K
+        log(f"bench: {name} schedule {res[name]:.2f} s")
+    print(json.dumps({"metric": "K-build s, 4000-atom s+p slab, tau=1e-8, mixed, learned vs bound-only scheduling",
+                      "value": st["quartets"] / res["mlp"], "unit": "quartets/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": 1e3 * res["mlp"], "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+                      "config": {"workload": f"{s.nbf // 4}-atom s+p slab 40x40x25 A, n={s.nbf}", "nbf": s.nbf},
+                      "mlp_s": res["mlp"], "bound_s": res["bound"], "mlp_gain": res["bound"] / res["mlp"],
+                      "train_samples": int(len(t)), "train_loss": loss, "quartets": st["quartets"],
+                      "K_bitwise_equal": bool(torch.equal(Ks["bound"], Ks["mlp"]))}))
 
 
 if __name__ == "__main__":
