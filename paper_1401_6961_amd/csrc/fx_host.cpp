@@ -689,27 +689,58 @@ static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
     const bool sched = c.schedule != FX_SCHED_NONE;
     const bool use_mlp = c.schedule == FX_SCHED_MLP && c.cm;
     const int nbins = 32;
-    float4* feat = nullptr;
-    float* cost = nullptr;
-    int* flags = nullptr;
-    uint8_t* key = nullptr;
-    long* bpos = nullptr;
-    int* order = nullptr;
-    float* times = nullptr;
-    long* bpartial = nullptr;
-    if (sched || c.rec) {
-        feat = A.get<float4>(maxlist);
-        cost = A.get<float>(maxlist);
-        if (sched) {
-            flags = A.get<int>((size_t)nbins * maxlist);
-            key = A.get<uint8_t>(maxlist);
-            bpos = A.get<long>((size_t)nbins * maxlist + 1);
-            order = A.get<int>(maxlist);
-            bpartial = A.get<long>(fx_scan_tiles((long)nbins * maxlist));
-        }
-        if (c.rec) times = A.get<float>(maxlist);
-    }
     const bool graph = c.use_graph && !c.profile && !c.rec;
+    // Independent class launches run on several streams so that the tail of
+    // one launch overlaps the next (they write disjoint K slots); each stream
+    // has its own scheduling buffers.  Recording, graph capture: one stream.
+    const int nstr = (graph || c.rec) ? 1 : FX_CLASS_STREAMS;
+    struct Lane {
+        hipStream_t s = nullptr;
+        float4* feat = nullptr;
+        float* cost = nullptr;
+        int* flags = nullptr;
+        uint8_t* key = nullptr;
+        long* bpos = nullptr;
+        int* order = nullptr;
+        long* bpartial = nullptr;
+        long* total = nullptr;
+    };
+    std::vector<Lane> lanes(nstr);
+    float* times = nullptr;
+    for (auto& ln : lanes) {
+        if (sched || c.rec) {
+            ln.feat = A.get<float4>(maxlist);
+            ln.cost = A.get<float>(maxlist);
+        }
+        if (sched) {
+            ln.flags = A.get<int>((size_t)nbins * maxlist);
+            ln.key = A.get<uint8_t>(maxlist);
+            ln.bpos = A.get<long>((size_t)nbins * maxlist + 1);
+            ln.order = A.get<int>(maxlist);
+            ln.bpartial = A.get<long>(fx_scan_tiles((long)nbins * maxlist));
+            ln.total = A.get<long>(1);
+        }
+    }
+    if (c.rec) times = A.get<float>(maxlist);
+    struct StreamSet {
+        std::vector<hipStream_t> s;
+        std::vector<hipEvent_t> e;
+        ~StreamSet() {
+            for (auto x : e) (void)hipEventDestroy(x);
+            for (auto x : s) (void)hipStreamDestroy(x);
+        }
+    } ss;
+    if (nstr > 1) {
+        hipEvent_t start;
+        FX_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+        ss.e.push_back(start);
+        FX_HIP(hipEventRecord(start, st));
+        for (auto& ln : lanes) {
+            FX_HIP(hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking));
+            ss.s.push_back(ln.s);
+            FX_HIP(hipStreamWaitEvent(ln.s, start, 0));
+        }
+    }
     hipGraph_t gr = nullptr;
     // Capture on a library-owned stream (the caller's may be the legacy default
     // stream, which cannot be captured); the graph is then launched on `st`.
@@ -725,6 +756,8 @@ static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
         FX_HIP(hipStreamBeginCapture(cap.s, hipStreamCaptureModeThreadLocal));
         st = cap.s;
     }
+    if (nstr == 1) lanes[0].s = st;
+    int next_lane = 0;
     std::vector<float> hfeat, htime;
     FxClassArgs args{};
     args.boys = segs[0]->T->boys;
@@ -755,14 +788,17 @@ static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
                                   (float)fx_class_hrr_flops[cls] + 1.f);
                     args.order = nullptr;
                     args.times = nullptr;
-                    if (feat) {
+                    Lane& ln = lanes[next_lane];
+                    next_lane = (next_lane + 1) % nstr;
+                    hipStream_t ls = ln.s;
+                    if (ln.feat) {
                         long o = 0;
                         for (auto* g : segs) {
                             const long n = g->bounds[k2 + 1] - g->bounds[k2];
                             if (n)
                                 fx_launch_unit_features(g->units + 3 * g->bounds[k2], n, g->sys.bc_off, g->sys.cls_off,
                                                         lb * 3 + lc, g->T->basis.nprim, g->T->qrow, class_cost,
-                                                        feat + o, st);
+                                                        ln.feat + o, ls);
                             o += n;
                         }
                     }
@@ -770,12 +806,12 @@ static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
                         // predicted log2 cost per unit: the learned model, or the
                         // bound-only estimate log2(class flops * nprim_a nprim_d * entries)
                         if (use_mlp)
-                            fx_launch_mlp_predict(c.cm->dW, c.cm->dnorm, feat, args.nunits, cost, st);
+                            fx_launch_mlp_predict(c.cm->dW, c.cm->dnorm, ln.feat, args.nunits, ln.cost, ls);
                         else
-                            fx_launch_bound_cost(feat, args.nunits, cost, st);
-                        fx_launch_bin_order(cost, args.nunits, use_mlp ? 40.f : 48.f, 1.0f, nbins, flags, key, bpos,
-                                            bpartial, c.scan_total, order, st, fx_scan_i32);
-                        args.order = order;
+                            fx_launch_bound_cost(ln.feat, args.nunits, ln.cost, ls);
+                        fx_launch_bin_order(ln.cost, args.nunits, use_mlp ? 40.f : 48.f, 1.0f, nbins, ln.flags,
+                                            ln.key, ln.bpos, ln.bpartial, ln.total, ln.order, ls, fx_scan_i32);
+                        args.order = ln.order;
                     }
                     for (int pr = 0; pr < nprec; ++pr) {
                         if (c.rec) args.times = times;
@@ -786,23 +822,24 @@ static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
                         args.flags = g_flags[cls][pr];
                         const int grid = 0;
                         if (c.profile) {
+                            // events on the stream the kernel is launched on
                             ExCtx::Timed t{cls * 2 + pr, nullptr, nullptr};
                             FX_HIP(hipEventCreate(&t.a));
                             FX_HIP(hipEventCreate(&t.b));
-                            FX_HIP(hipEventRecord(t.a, st));
-                            fx_class_table[cls](pr, g_variant[cls][pr], args, grid, st);
-                            FX_HIP(hipEventRecord(t.b, st));
+                            FX_HIP(hipEventRecord(t.a, ls));
+                            fx_class_table[cls](pr, g_variant[cls][pr], args, grid, ls);
+                            FX_HIP(hipEventRecord(t.b, ls));
                             c.timed.push_back(t);
                         } else {
-                            fx_class_table[cls](pr, g_variant[cls][pr], args, grid, st);
+                            fx_class_table[cls](pr, g_variant[cls][pr], args, grid, ls);
                         }
                         if (c.rec) {
                             const long n = args.nunits;
                             hfeat.resize(4 * n);
                             htime.resize(n);
-                            FX_HIP(hipMemcpyAsync(hfeat.data(), feat, sizeof(float4) * n, hipMemcpyDeviceToHost, st));
-                            FX_HIP(hipMemcpyAsync(htime.data(), times, sizeof(float) * n, hipMemcpyDeviceToHost, st));
-                            FX_HIP(hipStreamSynchronize(st));
+                            FX_HIP(hipMemcpyAsync(hfeat.data(), ln.feat, sizeof(float4) * n, hipMemcpyDeviceToHost, ls));
+                            FX_HIP(hipMemcpyAsync(htime.data(), times, sizeof(float) * n, hipMemcpyDeviceToHost, ls));
+                            FX_HIP(hipStreamSynchronize(ls));
                             for (long u = 0; u < n; ++u) {
                                 for (int q = 0; q < 4; ++q) c.rec->feat.push_back(hfeat[4 * u + q]);
                                 c.rec->log2ns.push_back(std::log2(std::max(1.0, (double)htime[u] * c.tick_ns)));
@@ -812,6 +849,16 @@ static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
                     }
                 }
         }
+    if (nstr > 1) {
+        // join: the caller's stream waits for every class stream
+        for (auto& ln : lanes) {
+            hipEvent_t done;
+            FX_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+            ss.e.push_back(done);
+            FX_HIP(hipEventRecord(done, ln.s));
+            FX_HIP(hipStreamWaitEvent(st, done, 0));
+        }
+    }
     if (graph) {
         FX_HIP(hipStreamEndCapture(cap.s, &gr));
         st = launch_st;

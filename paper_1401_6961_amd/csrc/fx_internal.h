@@ -5,6 +5,11 @@
 
 #define FX_CLASS_WAVES 4          // waves (work units) per thread-variant workgroup
 #define FX_COOP_WAVES 2           // waves per cooperative-variant workgroup
+// Streams over which independent class launches are spread.  Kept at 1: a
+// run with 4 concurrent class streams ended in HSA_STATUS_ERROR_OUT_OF_RESOURCES
+// on a queue (the spilling d-class kernels need large per-queue scratch); the
+// multi-stream path stays switched off until that is understood.
+#define FX_CLASS_STREAMS 1
 
 // Boys table: row i holds F_j(T_i), j = 0..14 (highest m 8 + 6 Taylor terms),
 // then e^{-T_i} in column 15; T_i = i / 32, i = 0..FX_BOYS_NROW-1.
