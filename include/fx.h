@@ -101,6 +101,15 @@ typedef enum fx_schedule { FX_SCHED_BOUND = 0, FX_SCHED_MLP = 1, FX_SCHED_NONE =
 
 typedef struct fx_costmodel fx_costmodel;
 
+/* Use of the permutational symmetry of the integrals (Section IV, in the
+ * form that keeps every K block a gather).  For a symmetric density,
+ * (ab|cd) = (dc|ba) gives K_da = K_ad^T, so only the K blocks a <= d (tree
+ * order) are built and each also writes its transpose: half the quartets.
+ *   FX_SYM_AUTO: the library tests P for bitwise symmetry on the device
+ *                (one pass over P) and uses this when it holds;
+ *   FX_SYM_OFF:  every K block is built (any P). */
+typedef enum fx_symmetry { FX_SYM_AUTO = 0, FX_SYM_OFF = 1 } fx_symmetry;
+
 typedef struct fx_exchange_opts {
     int32_t precision;          /* fx_precision, default FX_PREC_FP64        */
     double fp32_threshold;      /* default 1e-5                              */
@@ -110,6 +119,7 @@ typedef struct fx_exchange_opts {
     int64_t max_frontier_entries; /* traversal chunking threshold, 0 = auto  */
     int32_t profile;            /* 1: time every class-kernel launch with HIP events on `stream` */
     int32_t use_graph;          /* 1: capture the class-kernel launch sequence in a hipGraph and launch it */
+    int32_t symmetry;           /* fx_symmetry, default FX_SYM_AUTO          */
 } fx_exchange_opts;
 
 /* Statistics of one fx_exchange_ex call (valid when the call returns). */
@@ -119,7 +129,7 @@ typedef struct fx_stats {
     int64_t frontier[FX_STATS_MAX_LEVELS];       /* surviving tasks per level */
     int64_t leaf_items;                          /* surviving leaf (A,D) pairs */
     int64_t units;                               /* K-block work units        */
-    int64_t quartets;                            /* computed shell quartets   */
+    int64_t quartets;                            /* evaluated shell quartets  */
     int64_t quartets_fp32;                       /* of which in FP32          */
     int64_t class_quartets[81];                  /* per (la lb|lc ld), ((la*3+lb)*3+lc)*3+ld */
     double prim_quartets;                        /* primitive quartets        */
@@ -132,6 +142,9 @@ typedef struct fx_stats {
     double class_flops[162];                     /* algorithmic flops          */
     int64_t class_prec_quartets[162];            /* computed quartets          */
     double seconds_traversal, seconds_eri, seconds_total; /* host wall clock */
+    int64_t quartets_covered;                    /* ordered quartets with beta > tau that K accounts for
+                                                    (evaluated ones plus the mirrors they stand for) */
+    int32_t symmetric_systems;                   /* systems built on the symmetric path */
 } fx_stats;
 
 /* Build the basis-function tree for a set of shells: normalisation, shell

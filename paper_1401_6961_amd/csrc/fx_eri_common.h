@@ -265,6 +265,9 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, long 
     }
     double* kslot = Sy.slots + (long)A.slot_index * Sy.n * Sy.n;
     if (lane < NA * ND) kslot[rowbase + (long)(lane / ND) * Sy.n + (lane % ND)] = outv;
+    // symmetric density: K_da = K_ad^T, and unit (d, a) does not exist
+    if (Sy.sym && a != d && lane < NA * ND)
+        kslot[(long)(Bs.f0[d] + lane % ND) * Sy.n + Bs.f0[a] + lane / ND] = outv;
     if (A.times && lane == 0) A.times[u] = (float)(wall_clock64() - t_start);
     if (A.counters) {
         long np = npq;
@@ -273,6 +276,7 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, long 
         if (lane == 0) {
             atomicAdd(A.counters, (unsigned long long)nq);
             atomicAdd(A.counters + 1, (unsigned long long)np);
+            if (Sy.sym && a != d) atomicAdd(A.counters + 2, (unsigned long long)nq);
         }
     }
 }

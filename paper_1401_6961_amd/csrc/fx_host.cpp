@@ -537,6 +537,7 @@ struct SysCtx {
     double* Pn = nullptr;
     std::vector<double*> Psq;
     double* slots = nullptr;
+    int sym = 0;                    // symmetric density: only K blocks a <= d are built
 };
 
 // a leaf-level traversal chunk, ready for the class launches
@@ -606,7 +607,7 @@ static std::unique_ptr<LeafSeg> prepare_seg(ExCtx& c, SysCtx& sc, const Frontier
     if (c.stats) c.stats->leaf_items += nitems;
     int* cnt = A.get<int>(9 * nitems);
     long* upos = A.get<long>(9 * nitems + 1);
-    fx_launch_unit_count(f.ad, nitems, T->basis.leaf_lofs, cnt, st);
+    fx_launch_unit_count(f.ad, nitems, T->basis.leaf_lofs, T->basis.leaf_lsh, sc.sym, cnt, st);
     fx_scan_i32(cnt, 9 * nitems, upos, scan_partial(c, A, 9 * nitems), c.scan_total, st);
     for (int k = 0; k < 9; ++k)
         FX_HIP(hipMemcpyAsync(&seg->bounds[k], upos + (long)k * nitems, sizeof(long), hipMemcpyDeviceToHost, st));
@@ -615,7 +616,7 @@ static std::unique_ptr<LeafSeg> prepare_seg(ExCtx& c, SysCtx& sc, const Frontier
     const long nunits = seg->bounds[9];
     if (c.stats) c.stats->units += nunits;
     seg->units = A.get<int>(3 * std::max(1L, nunits));
-    fx_launch_unit_write(f.ad, nitems, 0, T->basis.leaf_lofs, T->basis.leaf_lsh, upos, seg->units, st);
+    fx_launch_unit_write(f.ad, nitems, 0, T->basis.leaf_lofs, T->basis.leaf_lsh, sc.sym, upos, seg->units, st);
     A.release(cnt);
     A.release(upos);
     FxSys& Y = seg->sys;
@@ -627,6 +628,7 @@ static std::unique_ptr<LeafSeg> prepare_seg(ExCtx& c, SysCtx& sc, const Frontier
     Y.bc = f.bc;
     Y.cls_off = nullptr;
     Y.slots = sc.slots;
+    Y.sym = sc.sym;
     const long ne = std::max(1L, f.e_count);
     if (T->single_shell_leaves) {
         int2* sorted = A.get<int2>(ne);
@@ -818,7 +820,7 @@ static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
                         args.mode = c.precision == FX_PREC_MIXED ? (pr ? FX_MODE_MIXED_LO : FX_MODE_MIXED_HI)
                                                                  : FX_MODE_ALL;
                         args.slot_index = slot_index(c, lb, lc, pr);
-                        args.counters = c.counters + (cls * 2 + pr) * 2;
+                        args.counters = c.counters + (cls * 2 + pr) * 3;
                         args.flags = g_flags[cls][pr];
                         const int grid = 0;
                         if (c.profile) {
@@ -912,6 +914,7 @@ static void traverse(ExCtx& c, SysCtx& sc, int k, const Frontier& f) {
     L.Psq = sc.Psq[k + 1];
     L.nk1 = (int)T->levels[k + 1].sL.size();
     L.tau2 = c.tau * c.tau;
+    L.sym = sc.sym;
     const long nm = 4 * f.e_count;
     uint8_t* mask = A.get<uint8_t>(nm);
     long* pos = A.get<long>(nm + 1);
@@ -989,6 +992,7 @@ static fx_exchange_opts checked_opts(const fx_exchange_opts* opts) {
     if (o.schedule < 0 || o.schedule > 2) fx_fail(FX_ERR_INVALID_ARG, "bad schedule");
     if (!std::isfinite(o.alpha) || !std::isfinite(o.beta)) fx_fail(FX_ERR_INVALID_ARG, "alpha/beta not finite");
     if (o.precision == FX_PREC_MIXED && !(o.fp32_threshold >= 0.0)) fx_fail(FX_ERR_INVALID_ARG, "bad fp32_threshold");
+    if (o.symmetry != FX_SYM_AUTO && o.symmetry != FX_SYM_OFF) fx_fail(FX_ERR_INVALID_ARG, "bad symmetry");
     return o;
 }
 
@@ -1027,8 +1031,8 @@ static void exchange_many(const fx_tree* const* trees, const double* const* Ps, 
     for (int i = 0; i < count; ++i) lmax = std::max(lmax, trees[i]->lmax);
     c.L = lmax + 1;
     c.nslot = c.L * c.L * (o.precision == FX_PREC_MIXED ? 2 : 1);
-    c.counters = A.get<unsigned long long>(81 * 2 * 2);
-    FX_HIP(hipMemsetAsync(c.counters, 0, sizeof(unsigned long long) * 81 * 4, st));
+    c.counters = A.get<unsigned long long>(81 * 2 * 3);
+    FX_HIP(hipMemsetAsync(c.counters, 0, sizeof(unsigned long long) * 81 * 2 * 3, st));
     c.scan_partial_cap = 1 << 16;
     c.scan_partial = A.get<long>(c.scan_partial_cap);
     c.scan_total = A.get<long>(1);
@@ -1056,6 +1060,17 @@ static void exchange_many(const fx_tree* const* trees, const double* const* Ps, 
                 fx_launch_level_up(sc.Psq[k + 1], (int)T->levels[k + 1].sL.size(), T->d_ch0[k], T->d_nch[k], nk,
                                    sc.Psq[k], st);
         }
+        // K symmetry: with a bitwise symmetric P, K_da = K_ad^T, so only the
+        // K blocks on and above the diagonal (tree order) are built.
+        sc.sym = 0;
+        if (o.symmetry == FX_SYM_AUTO && (n + 31) / 32 <= 65535) {
+            int* flag = A.get<int>(1);
+            fx_launch_fill_i32(flag, 1, 0, st);
+            fx_launch_psym(sc.P, n, flag, st);
+            sc.sym = read1(flag, st) == 0 ? 1 : 0;
+            A.release(flag);
+        }
+        if (stats) stats->symmetric_systems += sc.sym;
         sc.slots = A.get<double>((size_t)c.nslot * nn);
         fx_launch_fill(sc.slots, (long)c.nslot * nn, 0.0, st);
         FX_HIP(hipGetLastError());
@@ -1097,15 +1112,17 @@ static void exchange_many(const fx_tree* const* trees, const double* const* Ps, 
             }
         }
     } evguard{c};
-    std::vector<unsigned long long> cnt(81 * 4);
+    std::vector<unsigned long long> cnt(81 * 2 * 3);
     FX_HIP(hipMemcpyAsync(cnt.data(), c.counters, sizeof(unsigned long long) * cnt.size(), hipMemcpyDeviceToHost, st));
     FX_HIP(hipStreamSynchronize(st));
     if (stats) {
         for (int cls = 0; cls < 81; ++cls)
             for (int pr = 0; pr < 2; ++pr) {
-                const unsigned long long q = cnt[(cls * 2 + pr) * 2], pq = cnt[(cls * 2 + pr) * 2 + 1];
+                const unsigned long long q = cnt[(cls * 2 + pr) * 3], pq = cnt[(cls * 2 + pr) * 3 + 1];
+                const unsigned long long qm = cnt[(cls * 2 + pr) * 3 + 2];
                 stats->class_quartets[cls] += (int64_t)q;
                 stats->quartets += (int64_t)q;
+                stats->quartets_covered += (int64_t)(q + qm);
                 if (pr) stats->quartets_fp32 += (int64_t)q;
                 stats->prim_quartets += (double)pq;
                 const double fl = (double)pq * fx_class_vrr_flops[cls] + (double)q * fx_class_hrr_flops[cls];

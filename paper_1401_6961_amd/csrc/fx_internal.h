@@ -56,6 +56,7 @@ struct FxSys {
     const int2* bc;                   // (B, C) leaf nodes
     const long* cls_off;              // single-shell leaves: per item 10 class offsets, else null
     double* slots;                    // K slots of this system, n*n each
+    int sym;                          // 1: only units a <= d (tree order) exist; each writes K_ad and K_da
 };
 
 // launch options (autotuned per class and precision)
@@ -83,7 +84,8 @@ struct FxClassArgs {
     double tau, thr;
     int mode;                         // FX_MODE_*
     int flags;                        // FX_LAUNCH_*
-    unsigned long long* counters;     // computed quartets (nullable)
+    unsigned long long* counters;     // [3]: quartets, primitive quartets, quartets that also stand
+                                      // for their mirror (symmetric system, a != d) (nullable)
     float* times;                     // per-unit wall-clock ticks (nullable; timing probes)
 };
 

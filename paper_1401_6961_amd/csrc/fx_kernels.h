@@ -18,6 +18,7 @@ struct FxLevelArgs {
     const double* Psq;
     int nk1;
     double tau2;
+    int sym;               // keep only children with A_i <= D_l (symmetric density)
 };
 
 struct FxPrimPair;
@@ -36,9 +37,12 @@ void fx_launch_expand_adwrite(const FxLevelArgs& L, const long* pos, const int* 
                               long* bc_off_next, long total_entries, long total_ads, hipStream_t st);
 void fx_launch_expand_write(const FxLevelArgs& L, const uint8_t* mask, const long* pos, const long* adpos,
                             int2* bc_next, int* parent_next, hipStream_t st);
-void fx_launch_unit_count(const int2* items, long nitems, const int* leaf_lofs, int* cnt, hipStream_t st);
+void fx_launch_unit_count(const int2* items, long nitems, const int* leaf_lofs, const int* leaf_lsh, int sym, int* cnt,
+                          hipStream_t st);
 void fx_launch_unit_write(const int2* items, long nitems, long item_base, const int* leaf_lofs, const int* leaf_lsh,
-                          const long* upos, int* units, hipStream_t st);
+                          int sym, const long* upos, int* units, hipStream_t st);
+// flag <- 1 if P (n x n) is not bitwise symmetric; flag must be 0 on entry
+void fx_launch_psym(const double* P, long n, int* flag, hipStream_t st);
 void fx_launch_class_sort(const long* bc_off, const int2* bc, long nitems, const int* l, int2* out, long* cls_off,
                           hipStream_t st);
 void fx_launch_fill(double* x, long n, double v, hipStream_t st);

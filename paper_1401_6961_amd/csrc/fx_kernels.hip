@@ -234,7 +234,10 @@ void fx_scan_i32(const int* in, long n, long* out, long* partial, long* total_de
 // with squared Frobenius block norms at level k+1.  Each norm bounds every
 // contained shell-level norm, so no quartet with beta > tau is lost; the
 // margin absorbs rounding.  Output order: child AD (parent AD, i, l) major,
-// then (parent entry, j, k), which is deterministic.
+// then (parent entry, j, k), which is deterministic.  With a symmetric
+// density (L.sym) only children with A_i <= D_l are kept: nodes of a level
+// are ordered by their shell ranges, so this keeps exactly the K blocks on
+// and above the diagonal (in tree order), and K_DA is the transpose of K_AD.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ long fx_seg_index(const FxLevelArgs& L, int p, int il, long e) {
@@ -252,7 +255,7 @@ __global__ void fx_k_expand_mask(FxLevelArgs L, uint8_t* __restrict__ mask) {
     const int2 bc = L.bc[e];
     const int i = il >> 1, l = il & 1;
     uint8_t m = 0;
-    if (i < L.nch[ad.x] && l < L.nch[ad.y]) {
+    if (i < L.nch[ad.x] && l < L.nch[ad.y] && (!L.sym || L.ch0[ad.x] + i <= L.ch0[ad.y] + l)) {
         const int Ai = L.ch0[ad.x] + i, Dl = L.ch0[ad.y] + l;
         const int nB = L.nch[bc.x], nC = L.nch[bc.y];
         for (int j = 0; j < nB; ++j) {
@@ -345,26 +348,39 @@ void fx_launch_expand_write(const FxLevelArgs& L, const uint8_t* mask, const lon
 // shells a in A with l = la and d in D with l = ld.  Units are laid out per
 // (la, ld) list in item order, then a, then d.
 // ---------------------------------------------------------------------------
+// On a diagonal item (A == A) of a symmetric build only the pairs a <= d.
+__device__ __forceinline__ int fx_unit_pairs(const int* __restrict__ leaf_lsh, int oa, int na, int od, int nd,
+                                             bool diag) {
+    if (!diag) return na * nd;
+    int c = 0;
+    for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nd; ++j) c += leaf_lsh[oa + i] <= leaf_lsh[od + j];
+    return c;
+}
+
 __global__ void fx_k_unit_count(const int2* __restrict__ items, long nitems, const int* __restrict__ leaf_lofs,
-                                int* __restrict__ cnt) {
+                                const int* __restrict__ leaf_lsh, int sym, int* __restrict__ cnt) {
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nitems) return;
     const int2 ad = items[p];
+    const bool diag = sym && ad.x == ad.y;
     for (int la = 0; la < 3; ++la)
         for (int ld = 0; ld < 3; ++ld) {
-            const int na = leaf_lofs[ad.x * 4 + la + 1] - leaf_lofs[ad.x * 4 + la];
-            const int nd = leaf_lofs[ad.y * 4 + ld + 1] - leaf_lofs[ad.y * 4 + ld];
-            cnt[(long)(la * 3 + ld) * nitems + p] = na * nd;
+            const int oa = leaf_lofs[ad.x * 4 + la], na = leaf_lofs[ad.x * 4 + la + 1] - oa;
+            const int od = leaf_lofs[ad.y * 4 + ld], nd = leaf_lofs[ad.y * 4 + ld + 1] - od;
+            cnt[(long)(la * 3 + ld) * nitems + p] = fx_unit_pairs(leaf_lsh, oa, na, od, nd, diag);
         }
 }
 
-void fx_launch_unit_count(const int2* items, long nitems, const int* leaf_lofs, int* cnt, hipStream_t st) {
+void fx_launch_unit_count(const int2* items, long nitems, const int* leaf_lofs, const int* leaf_lsh, int sym, int* cnt,
+                          hipStream_t st) {
     if (nitems > 0)
-        hipLaunchKernelGGL(fx_k_unit_count, dim3((nitems + 255) / 256), dim3(256), 0, st, items, nitems, leaf_lofs, cnt);
+        hipLaunchKernelGGL(fx_k_unit_count, dim3((nitems + 255) / 256), dim3(256), 0, st, items, nitems, leaf_lofs,
+                           leaf_lsh, sym, cnt);
 }
 
 __global__ void fx_k_unit_write(const int2* __restrict__ items, long nitems, long item_base,
-                                const int* __restrict__ leaf_lofs, const int* __restrict__ leaf_lsh,
+                                const int* __restrict__ leaf_lofs, const int* __restrict__ leaf_lsh, int sym,
                                 const long* __restrict__ upos, int* __restrict__ units) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nitems * 9) return;
@@ -372,11 +388,13 @@ __global__ void fx_k_unit_write(const int2* __restrict__ items, long nitems, lon
     const long p = t - (long)cls * nitems;
     const int la = cls / 3, ld = cls % 3;
     const int2 ad = items[p];
+    const bool diag = sym && ad.x == ad.y;
     const int oa = leaf_lofs[ad.x * 4 + la], na = leaf_lofs[ad.x * 4 + la + 1] - oa;
     const int od = leaf_lofs[ad.y * 4 + ld], nd = leaf_lofs[ad.y * 4 + ld + 1] - od;
     long o = upos[t];
     for (int i = 0; i < na; ++i)
         for (int j = 0; j < nd; ++j) {
+            if (diag && leaf_lsh[oa + i] > leaf_lsh[od + j]) continue;
             units[3 * o] = (int)(item_base + p);
             units[3 * o + 1] = leaf_lsh[oa + i];
             units[3 * o + 2] = leaf_lsh[od + j];
@@ -385,11 +403,38 @@ __global__ void fx_k_unit_write(const int2* __restrict__ items, long nitems, lon
 }
 
 void fx_launch_unit_write(const int2* items, long nitems, long item_base, const int* leaf_lofs, const int* leaf_lsh,
-                          const long* upos, int* units, hipStream_t st) {
+                          int sym, const long* upos, int* units, hipStream_t st) {
     const long n = nitems * 9;
     if (n > 0)
         hipLaunchKernelGGL(fx_k_unit_write, dim3((n + 255) / 256), dim3(256), 0, st, items, nitems, item_base, leaf_lofs,
-                           leaf_lsh, upos, units);
+                           leaf_lsh, sym, upos, units);
+}
+
+// ---------------------------------------------------------------------------
+// Bitwise symmetry test of P: 32x32 tiles (bi <= bj) and their mirror tiles
+// staged through LDS, so both reads are coalesced.  Any mismatch (NaN
+// included) sets *flag = 1; every writer stores the same value.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fx_k_psym(const double* __restrict__ P, long n, int* __restrict__ flag) {
+    __shared__ double t1[32][33], t2[32][33];
+    const long bi = blockIdx.y, bj = blockIdx.x;
+    if (bi > bj) return;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const long i = bi * 32 + r, j = bj * 32 + tx;
+        t1[r][tx] = (i < n && j < n) ? P[i * n + j] : 0.0;
+        const long i2 = bj * 32 + r, j2 = bi * 32 + tx;
+        t2[r][tx] = (i2 < n && j2 < n) ? P[i2 * n + j2] : 0.0;
+    }
+    __syncthreads();
+    bool bad = false;
+    for (int r = ty; r < 32; r += 8) bad |= !(t1[r][tx] == t2[tx][r]);
+    if (bad) *flag = 1;
+}
+
+void fx_launch_psym(const double* P, long n, int* flag, hipStream_t st) {
+    const long nb = (n + 31) / 32;
+    if (nb > 0) hipLaunchKernelGGL(fx_k_psym, dim3(nb, nb), dim3(256), 0, st, P, n, flag);
 }
 
 // ---------------------------------------------------------------------------

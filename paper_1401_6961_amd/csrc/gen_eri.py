@@ -376,6 +376,180 @@ def gen_class(la, lb, lc, ld, real, diag=False):
     return "\n".join(out), vem.flops, hem.flops + cflops
 
 
+def gen_class_staged(la, lb, lc, ld, real):
+    """Staged form of the same routine, for classes whose [e0|f0] block does
+    not fit in registers.  Same arithmetic, different data movement: the
+    accumulated [e0|f0] block X and the bra-transferred block Y = (x1 x2|f)
+    live in per-lane private memory (lane-interleaved, so each access of a
+    wave is one coalesced transaction), each written once per primitive
+    quartet and read once:
+
+      1. per primitive quartet: Boys, VRR; every target [e0|f0] is added
+         into X as soon as it is formed;
+      2. bra HRR one ket column f at a time: read X[., f], write Y[., f];
+      3. ket HRR one bra row at a time: read Y[row, .], form the row's
+         integrals and contract each into kacc at once.
+
+    Returns (code, flops_per_prim, flops_per_contracted) like gen_class."""
+    ls = (la, lb, lc, ld)
+    o = orientation(la, lb, lc, ld)
+    L = [ls[x] for x in o]
+    body = build_body(real, L)
+    vem, targets, tnames = body["vem"], body["targets"], body["tnames"]
+    Lsum = sum(L)
+    comps = [cart(l) for l in ls]
+    icomp = [cart(l) for l in L]
+    fcols = [f for lf in range(L[2], L[2] + L[3] + 1) for f in cart(lf)]
+    fidx = {f: k for k, f in enumerate(fcols)}
+    nrow = len(icomp[0]) * len(icomp[1])
+    NX, NY = len(targets), nrow * len(fcols)
+    out = []
+    w = out.append
+    cls = f"{LNAME[la]}{LNAME[lb]}{LNAME[lc]}{LNAME[ld]}"
+    prec = "f32" if real == "float" else "f64"
+    w(f"// class ({LNAME[la]}{LNAME[lb]}|{LNAME[lc]}{LNAME[ld]}) {prec}, staged; internal order "
+      f"({'abcd'[o[0]]}{'abcd'[o[1]]}|{'abcd'[o[2]]}{'abcd'[o[3]]}); X {NX}, Y {NY} private slots")
+    w(f"__device__ __forceinline__ void eri_{cls}_{prec}(const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc,")
+    w(f"    const FxShellRef& rd, const FxDevBasis& B,")
+    w(f"    const double* __restrict__ boys_tab, const double* __restrict__ Pmat, long ldp, double* __restrict__ kacc) {{")
+    roles = ["ra", "rb", "rc", "rd"]
+    x = [roles[r] for r in o]
+    w(f"  const FxShellRef& x1 = {x[0]}; const FxShellRef& x2 = {x[1]}; const FxShellRef& x3 = {x[2]}; const FxShellRef& x4 = {x[3]};")
+    # The asm statement hides the arrays' addresses from the optimiser, so
+    # they stay in private memory instead of being promoted to registers.
+    w(f"  {real} Xs[{NX}], Ys[{NY}];")
+    w(f"  __attribute__((address_space(5))) {real}* X = (__attribute__((address_space(5))) {real}*)Xs;")
+    w(f"  __attribute__((address_space(5))) {real}* Y = (__attribute__((address_space(5))) {real}*)Ys;")
+    w("  asm volatile(\"\" : \"+v\"(X), \"+v\"(Y));")
+    w("  const double ABx = x1.x - x2.x, ABy = x1.y - x2.y, ABz = x1.z - x2.z;")
+    w("  const double CDx = x3.x - x4.x, CDy = x3.y - x4.y, CDz = x3.z - x4.z;")
+    w("  const long Nt = B.ntprim;")
+    w("  const FxPrimPair* __restrict__ pab = B.pp + (long)x1.pofs * Nt + x2.pofs;")
+    w("  const FxPrimPair* __restrict__ pcd = B.pp + (long)x3.pofs * Nt + x4.pofs;")
+    w("  bool first = true;")
+    w("  for (int i1 = 0; i1 < x1.nprim; ++i1) {")
+    w("    for (int i2 = 0; i2 < x2.nprim; ++i2) {")
+    w("      const FxPrimPair bra = pab[i1 * Nt + i2];")
+    w("      const double p = bra.p, op = bra.op, Px = bra.Px, Py = bra.Py, Pz = bra.Pz;")
+    w("      for (int i3 = 0; i3 < x3.nprim; ++i3) {")
+    w("        for (int i4 = 0; i4 < x4.nprim; ++i4) {")
+    w("          const FxPrimPair ket = pcd[i3 * Nt + i4];")
+    w("          const double q = ket.p, oq = ket.op, Qx = ket.Px, Qy = ket.Py, Qz = ket.Pz;")
+    w("          const double ppq = p + q, oppq = 1.0 / ppq, rho = p * q * oppq;")
+    w("          const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;")
+    w("          const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);")
+    w("          const double pref = FX_TWO_PI_POW_2_5 * op * oq * sqrt(oppq) * bra.K * ket.K;")
+    w(f"          double F[{Lsum + 1}];")
+    w(f"          fx_boys<{Lsum}>(T, boys_tab, F);")
+    for m in range(Lsum + 1):
+        w(f"          const {real} s{m} = ({real})(pref * F[{m}]);")
+    w("          const double Wx = (p * Px + q * Qx) * oppq, Wy = (p * Py + q * Qy) * oppq, Wz = (p * Pz + q * Qz) * oppq;")
+    for c in "xyz":
+        w(f"          const {real} PA{c} = ({real})(P{c} - x1.{c}), WP{c} = ({real})(W{c} - P{c});")
+        w(f"          const {real} QC{c} = ({real})(Q{c} - x3.{c}), WQ{c} = ({real})(W{c} - Q{c});")
+    w(f"          const {real} oo2p = ({real})(0.5 * op), oo2q = ({real})(0.5 * oq), oo2pq = ({real})(0.5 * oppq);")
+    w(f"          const {real} oo2p_rp = ({real})(0.5 * op * rho * op), oo2q_rq = ({real})(0.5 * oq * rho * oq);")
+    w("          (void)PAx; (void)PAy; (void)PAz; (void)WPx; (void)WPy; (void)WPz;")
+    w("          (void)QCx; (void)QCy; (void)QCz; (void)WQx; (void)WQy; (void)WQz;")
+    w("          (void)oo2p; (void)oo2q; (void)oo2pq; (void)oo2p_rp; (void)oo2q_rq;")
+    # store each target right after the statement that forms it
+    tpos = {nm: k for k, nm in enumerate(tnames)}
+    zero = "0.0f" if real == "float" else "0.0"
+    for line in vem.lines:
+        w("          " + line)
+        nm = line.split(" = ", 1)[0].split()[-1]
+        if nm in tpos:
+            k = tpos.pop(nm)
+            w(f"          X[{k}] = (first ? {zero} : X[{k}]) + {nm};")
+    for nm, k in tpos.items():     # targets that are base values s_m
+        w(f"          X[{k}] = (first ? {zero} : X[{k}]) + {nm};")
+    w("          first = false;")
+    w("        }")
+    w("      }")
+    w("    }")
+    w("  }")
+    w(f"  const {real} ABx_ = ({real})ABx, ABy_ = ({real})ABy, ABz_ = ({real})ABz;")
+    w(f"  const {real} CDx_ = ({real})CDx, CDy_ = ({real})CDy, CDz_ = ({real})CDz;")
+    w("  (void)ABx_; (void)ABy_; (void)ABz_; (void)CDx_; (void)CDy_; (void)CDz_;")
+    idx = {t: k for k, t in enumerate(targets)}
+    hflops = 0
+    # 2. bra HRR per ket column
+    for f in fcols:
+        hem = Emitter(real)
+        loads = {}
+
+        def xval(e, f_, hem=hem, loads=loads):
+            k = idx[(e, f_)]
+            if k not in loads:
+                nm = hem.new("x")
+                hem.emit(f"const {real} {nm} = X[{k}];")
+                loads[k] = nm
+            return loads[k]
+        hrr = HRR(hem, xval)
+        res = []
+        for ia, a in enumerate(icomp[0]):
+            for ib, b in enumerate(icomp[1]):
+                res.append(((ia * len(icomp[1]) + ib) * len(fcols) + fidx[f], hrr.bra(a, b, f)))
+        w("  {")
+        for line in hem.lines:
+            w("    " + line)
+        for k, nm in res:
+            w(f"    Y[{k}] = {nm};")
+        w("  }")
+        hflops += hem.flops
+    # 3. ket HRR per bra row, contraction
+    nd = len(comps[3])
+    index = [{t: k for k, t in enumerate(comps[r])} for r in range(4)]
+    pvs = {}
+    for jn, nu in enumerate(comps[1]):
+        for kl, lam in enumerate(comps[2]):
+            fac = comp_factor(nu) * comp_factor(lam)
+            pv = f"pv{jn}_{kl}"
+            pvs[(jn, kl)] = pv
+            if abs(fac - 1.0) < 1e-15:
+                w(f"  const double {pv} = Pmat[{jn} * ldp + {kl}];")
+            else:
+                w(f"  const double {pv} = Pmat[{jn} * ldp + {kl}] * {fac!r};")
+                hflops += 1
+    for ia, a in enumerate(icomp[0]):
+        for ib, b in enumerate(icomp[1]):
+            hem = Emitter(real)
+            row = (ia * len(icomp[1]) + ib) * len(fcols)
+            loads = {}
+
+            def yval(a_, f_, hem=hem, loads=loads, row=row):
+                k = row + fidx[f_]
+                if k not in loads:
+                    nm = hem.new("y")
+                    hem.emit(f"const {real} {nm} = Y[{k}];")
+                    loads[k] = nm
+                return loads[k]
+            hrr = HRR(hem, None)
+            # bra(a, b, f) of this row is the staged Y value
+            for f in fcols:
+                hrr.memo[("b", a, b, f)] = None
+            hrr.bra = lambda a_, b_, f_, yv=yval: yv(a_, f_)
+            w("  {")
+            contr = []
+            for c in icomp[2]:
+                for d in icomp[3]:
+                    nm = hrr.full(a, b, c, d)
+                    ext = [None] * 4
+                    for pos, role in enumerate(o):
+                        ext[role] = (a, b, c, d)[pos]
+                    im, jn, kl, ls_ = (index[r][ext[r]] for r in range(4))
+                    contr.append((im * nd + ls_, nm, pvs[(jn, kl)]))
+            for line in hem.lines:
+                w("    " + line)
+            for slot, nm, pv in contr:
+                w(f"    kacc[{slot}] += (double){nm} * {pv};")
+                hflops += 2
+            w("  }")
+            hflops += hem.flops
+    w("}")
+    return "\n".join(out), vem.flops, hflops
+
+
 def classes():
     return list(itertools.product(range(3), repeat=4))
 

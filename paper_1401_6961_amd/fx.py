@@ -17,6 +17,7 @@ _lib = None
 
 FX_PREC_FP64, FX_PREC_MIXED = 0, 1
 FX_SCHED_BOUND, FX_SCHED_MLP, FX_SCHED_NONE = 0, 1, 2
+FX_SYM_AUTO, FX_SYM_OFF = 0, 1
 
 
 class FxError(RuntimeError):
@@ -40,7 +41,7 @@ class fx_exchange_opts(ctypes.Structure):
                 ("schedule", ctypes.c_int32), ("costmodel", ctypes.c_void_p),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("max_frontier_entries", ctypes.c_int64), ("profile", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("symmetry", ctypes.c_int32)]
 
 
 class fx_train_opts(ctypes.Structure):
@@ -57,7 +58,8 @@ class fx_stats(ctypes.Structure):
                 ("class_seconds", ctypes.c_double * 162), ("class_launches", ctypes.c_int32 * 162),
                 ("class_flops", ctypes.c_double * 162), ("class_prec_quartets", ctypes.c_int64 * 162),
                 ("seconds_traversal", ctypes.c_double), ("seconds_eri", ctypes.c_double),
-                ("seconds_total", ctypes.c_double)]
+                ("seconds_total", ctypes.c_double), ("quartets_covered", ctypes.c_int64),
+                ("symmetric_systems", ctypes.c_int32)]
 
     def as_dict(self):
         return {"levels": self.levels, "frontier": list(self.frontier)[: self.levels],
@@ -67,7 +69,8 @@ class fx_stats(ctypes.Structure):
                 "prim_quartets": self.prim_quartets, "flops": self.flops, "chunks": self.chunks,
                 "graph_nodes": self.graph_nodes,
                 "seconds_traversal": self.seconds_traversal, "seconds_eri": self.seconds_eri,
-                "seconds_total": self.seconds_total,
+                "seconds_total": self.seconds_total, "quartets_covered": self.quartets_covered,
+                "symmetric_systems": self.symmetric_systems,
                 "class_seconds": np.array(self.class_seconds).reshape(81, 2),
                 "class_launches": np.array(self.class_launches).reshape(81, 2),
                 "class_flops": np.array(self.class_flops).reshape(81, 2),
@@ -255,11 +258,11 @@ def build_quadtree_from(system, **kw) -> Tree:
 
 
 def make_opts(precision=FX_PREC_FP64, fp32_threshold=1e-5, schedule=FX_SCHED_BOUND, costmodel=None, alpha=1.0,
-              beta=0.0, max_frontier_entries=0, profile=False, use_graph=False):
+              beta=0.0, max_frontier_entries=0, profile=False, use_graph=False, symmetry=FX_SYM_AUTO):
     return fx_exchange_opts(int(precision), float(fp32_threshold), int(schedule),
                             ctypes.c_void_p(costmodel.handle if costmodel is not None else None),
                             float(alpha), float(beta), int(max_frontier_entries), int(bool(profile)),
-                            int(bool(use_graph)))
+                            int(bool(use_graph)), int(symmetry))
 
 
 def fx_exchange(tree: Tree, P, tau, K, stream=None):

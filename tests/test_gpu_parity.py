@@ -26,6 +26,15 @@ def say(msg):
     print(msg, flush=True)
 
 
+def assert_symmetric_path_K(sys_, K):
+    """Off-diagonal shell blocks are written as exact transposes; blocks of a
+    shell with itself are symmetric to rounding."""
+    shell = np.repeat(np.arange(sys_.nshell), [(l + 1) * (l + 2) // 2 for l in sys_.l])
+    same = shell[:, None] == shell[None, :]
+    assert np.array_equal(K[~same], K.T[~same])
+    assert np.abs(K - K.T).max() <= 1e-13
+
+
 def gpu_exchange(sys_, tau, P=None, tree=None, **opts):
     if tree is None:
         tree = fx.build_quadtree_from(sys_)
@@ -56,12 +65,42 @@ def test_schwarz_norms(spd5):
 
 
 def test_all_classes_fp64(spd5):
-    say("gpu: all 81 classes fp64, spd5 tau=1e-11")
+    """Every K block built (symmetry off): per-class quartet counts equal the
+    oracle's exactly."""
+    say("gpu: all 81 classes fp64, spd5 tau=1e-11, symmetry off")
     Ko, sto = oracle.exchange(spd5, tau=1e-11)
     cnt, _, near = oracle.count(spd5, tau=1e-11)
-    Kg, st, _ = gpu_exchange(spd5, 1e-11)
+    Kg, st, _ = gpu_exchange(spd5, 1e-11, symmetry=fx.FX_SYM_OFF)
     assert near == 0
+    assert st["symmetric_systems"] == 0
     assert np.array_equal(st["class_quartets"], cnt)
+    assert st["quartets"] == sto["quartets"] == st["quartets_covered"]
+    assert np.abs(Kg - Ko).max() <= TOL64
+
+
+def test_all_classes_fp64_symmetric(spd5):
+    """Symmetric density: only K blocks a <= d are built, each writing its
+    transpose.  K is symmetric (exactly off the shell diagonal), matches the
+    oracle, and the quartets it accounts for (evaluated + mirrored) are
+    exactly the oracle's set."""
+    say("gpu: all 81 classes fp64, spd5 tau=1e-11, symmetric path")
+    Ko, sto = oracle.exchange(spd5, tau=1e-11)
+    Kg, st, _ = gpu_exchange(spd5, 1e-11)
+    assert st["symmetric_systems"] == 1
+    assert st["quartets_covered"] == sto["quartets"]
+    assert st["quartets"] < 0.6 * sto["quartets"]
+    assert_symmetric_path_K(spd5, Kg)
+    assert np.abs(Kg - Ko).max() <= TOL64
+
+
+def test_nonsymmetric_density_uses_full_path(spd5):
+    """A non-symmetric P is detected on the device; every block is built."""
+    say("gpu: non-symmetric density")
+    rng = np.random.default_rng(5)
+    P = spd5.P + 0.05 * rng.standard_normal(spd5.P.shape) * (np.abs(spd5.P) > 0)
+    Ko, sto = oracle.exchange(spd5, tau=1e-11, P=P)
+    Kg, st, _ = gpu_exchange(spd5, 1e-11, P=P)
+    assert st["symmetric_systems"] == 0
     assert st["quartets"] == sto["quartets"]
     assert np.abs(Kg - Ko).max() <= TOL64
 
@@ -92,11 +131,14 @@ def test_tiny_cube_config(request):
     say("gpu: 24-atom s+p cube, tau=1e-12")
     s = synthetic.config(0)
     Ko, sto = oracle.exchange(s)
-    Kg, st, _ = gpu_exchange(s, s.tau)
     assert sto["near_threshold"] == 0
+    Kg, st, _ = gpu_exchange(s, s.tau, symmetry=fx.FX_SYM_OFF)
     assert st["quartets"] == sto["quartets"]
     assert st["prim_quartets"] == sto["prim_quartets"]
     assert np.abs(Kg - Ko).max() <= TOL64
+    Ks, sts, _ = gpu_exchange(s, s.tau)
+    assert sts["symmetric_systems"] == 1 and sts["quartets_covered"] == sto["quartets"]
+    assert np.abs(Ks - Ko).max() <= TOL64
 
 
 @pytest.fixture(scope="module")
@@ -111,9 +153,13 @@ def test_chain_config(chain):
     s, Ko, sto = chain
     Kg, st, _ = gpu_exchange(s, s.tau)
     assert sto["near_threshold"] == 0
-    assert st["quartets"] == sto["quartets"]
+    assert st["quartets_covered"] == sto["quartets"]
     assert np.abs(Kg - Ko).max() <= TOL64
-    assert np.abs(Kg - Kg.T).max() <= 1e-12
+    assert_symmetric_path_K(s, Kg)
+    Kf, stf, _ = gpu_exchange(s, s.tau, symmetry=fx.FX_SYM_OFF)
+    assert stf["quartets"] == sto["quartets"]
+    assert np.abs(Kf - Ko).max() <= TOL64
+    assert np.abs(Kf - Kf.T).max() <= 1e-12
 
 
 def test_chunked_traversal_is_bitwise_identical(chain):
@@ -188,7 +234,7 @@ def test_cooperative_variants(spd5):
         assert len(saved) > 0
         Ko, sto = oracle.exchange(spd5, tau=1e-11)
         Kg, st, _ = gpu_exchange(spd5, 1e-11)
-        assert st["quartets"] == sto["quartets"]
+        assert st["quartets_covered"] == sto["quartets"]
         assert np.abs(Kg - Ko).max() <= TOL64
         Km, _, _ = gpu_exchange(spd5, 1e-11, precision=fx.FX_PREC_MIXED)
         assert np.abs(Km - Ko).max() <= 1e-7
