@@ -37,6 +37,31 @@ def cname(c):
     return f"({LNAME[c // 27]}{LNAME[(c // 9) % 3]}|{LNAME[(c // 3) % 3]}{LNAME[c % 3]})"
 
 
+GEN_SOURCES = ("paper_1401_6961_amd/csrc/gen_eri.py", "paper_1401_6961_amd/csrc/fx_eri_common.h",
+               "paper_1401_6961_amd/csrc/fx_internal.h")
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (profiles/hbm_traffic_*.md), provided the kernel sources hash to
+    the value recorded with the counters; (None, None) otherwise."""
+    import glob
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for p in GEN_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    gh = h.hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md"))):
+        m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+        if not m:
+            continue
+        rec = json.loads(m.group(1))
+        if rec.get("kernel") == kernel and rec.get("gen_hash") == gh:
+            return rec["traffic_bytes_per_launch"], os.path.relpath(path, ROOT)
+    return None, None
+
+
 def cpu_baseline(system, budget_s=15.0, seed=0):
     """Time the oracle on seeded random K blocks (a, d) of the same system."""
     import oracle
@@ -68,10 +93,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison build")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="cluster", choices=["cluster", "batched", "slab-mlp"],
+    ap.add_argument("--workload", default="cluster", choices=["cluster", "batched", "slab-mlp", "copy-probe"],
                     help="cluster: the headline 1000-atom s+p+d build; batched: 64 clusters in one batched "
                          "call vs 64 sequential builds; slab-mlp: 4000-atom s+p slab, learned vs bound-only "
-                         "scheduling")
+                         "scheduling; copy-probe: one elementwise copy of 1 GiB, to scale HBM byte counters")
     ap.add_argument("--no-tuning", action="store_true", help="ignore the autotuned kernel table")
     ap.add_argument("--no-symmetry", action="store_true", help="build every K block (no use of K = K^T)")
     args = ap.parse_args()
@@ -87,6 +112,8 @@ def main():
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    if args.workload == "copy-probe":
+        return copy_probe()
     tuned = 0 if args.no_tuning else autotune.apply()
     log(f"bench: {tuned} autotuned class entries applied")
     if args.workload == "batched":
@@ -133,8 +160,12 @@ def main():
     avg_launch_s = cs[c, p] / max(1, cl[c, p])
     achieved = per_launch_flops / avg_launch_s / 1e12
     peak = FP32_PEAK_TFLOPS if p else FP64_PEAK_TFLOPS
+    kname = f"fx_k_{cname(c)[1:3]}{cname(c)[4:6]}_{'f32' if p else 'f64'}"
+    traffic, traffic_src = profiled_traffic(kname)
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "kernel": f"fx_k_{cname(c)[1:3]}{cname(c)[4:6]}_{'f32' if p else 'f64'}",
+                "traffic": traffic, "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
+                "traffic_source": traffic_src,
+                "traffic_GBps": traffic / avg_launch_s / 1e9 if traffic else None, "kernel": kname,
                 "class": cname(c), "avg_launch_ms": 1e3 * avg_launch_s,
                 "flops_per_launch": per_launch_flops,
                 "all_class_kernels_tflops": float(cf.sum() / cs.sum() / 1e12) if cs.sum() > 0 else None}
@@ -186,6 +217,20 @@ def main():
            "cpu_baseline": cpu}
     out.update(extra)
     print(json.dumps(out))
+
+
+def copy_probe():
+    """One elementwise kernel that reads and writes 1 GiB each (after a
+    warm-up pass): the reference for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe": True, "bytes_read": 8 * n, "bytes_written": 8 * n, "dispatches": 2}))
 
 
 def bench_batched(args, log):
