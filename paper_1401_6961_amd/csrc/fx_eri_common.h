@@ -297,8 +297,18 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
 }
 
 // Thread variant: one quartet per lane.
+// FX_THREAD_MIN_WAVES_f64 / _f32 (set per class by the generator): the least
+// number of waves per SIMD the register allocation must allow.  Above 1 it
+// trades register spills for latency hiding in kernels that spill anyway.
+#ifndef FX_THREAD_MIN_WAVES_f64
+#define FX_THREAD_MIN_WAVES_f64 1
+#endif
+#ifndef FX_THREAD_MIN_WAVES_f32
+#define FX_THREAD_MIN_WAVES_f32 1
+#endif
 #define FX_THREAD_KERNEL(la, lb, lc, ld, cls, prec)                                                     \
-    __global__ __launch_bounds__(64 * FX_CLASS_WAVES) void fx_k_##cls##_##prec(FxClassArgs A) {        \
+    __global__ __launch_bounds__(64 * FX_CLASS_WAVES, FX_THREAD_MIN_WAVES_##prec) void                  \
+        fx_k_##cls##_##prec(FxClassArgs A) {                                                            \
         fx_class_body<la, lb, lc, ld, false, FX_CLASS_WAVES>(                                           \
             A, [](const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc, const FxShellRef& rd, \
                   const FxDevBasis& B, const double* bt, const double* P, long n, double* k, int) {       \

@@ -567,6 +567,14 @@ def pair_size(l1, l2):
 COOP_MIN, THREAD_MAX = 100, 1 << 30
 
 
+# Waves per SIMD that the register allocation of a one-quartet-per-lane
+# kernel must allow (default 1, i.e. up to 512 registers per lane).  Set from
+# measurement on the 1000-atom s+p+d cluster: only the (dd|dd) FP64 kernel,
+# which spills 15 KB per lane at one wave, ran faster at two (-21%); every
+# other spilling kernel ran as fast or slower.
+MIN_WAVES = {("dddd", "f64"): 2}
+
+
 def variants(la, lb, lc, ld):
     nacc = pair_size(la, lb) * pair_size(lc, ld)
     return (nacc < THREAD_MAX, nacc >= COOP_MIN)
@@ -591,6 +599,10 @@ def main(outdir):
         src = ["// Generated by gen_eri.py -- do not edit.", '#include "fx_eri_common.h"', ""]
         src += parts
         kind = "BOTH" if (th and co) else ("THREAD" if th else "COOP")
+        for prec in ("f64", "f32"):
+            mw = MIN_WAVES.get((cls, prec), 1)
+            if mw > 1:
+                src.append(f"#define FX_THREAD_MIN_WAVES_{prec} {mw}")
         src.append(f'FX_DEFINE_CLASS_KERNELS_{kind}({la}, {lb}, {lc}, {ld}, {cls})')
         path = os.path.join(outdir, f"eri_{cls}.hip")
         new = "\n".join(src) + "\n"
