@@ -9,6 +9,12 @@
 
 #define FX_TWO_PI_POW_2_5 34.98683665524972497   // 2 pi^{5/2}
 
+// compile-time flag of the staged routines: store (false) or add (true)
+template <bool B>
+struct FxAcc {
+    static constexpr bool value = B;
+};
+
 struct FxShellRef {
     double x, y, z;
     int nprim, pofs, idx;

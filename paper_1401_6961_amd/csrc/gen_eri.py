@@ -426,48 +426,48 @@ def gen_class_staged(la, lb, lc, ld, real):
     w("  const long Nt = B.ntprim;")
     w("  const FxPrimPair* __restrict__ pab = B.pp + (long)x1.pofs * Nt + x2.pofs;")
     w("  const FxPrimPair* __restrict__ pcd = B.pp + (long)x3.pofs * Nt + x4.pofs;")
-    w("  bool first = true;")
-    w("  for (int i1 = 0; i1 < x1.nprim; ++i1) {")
-    w("    for (int i2 = 0; i2 < x2.nprim; ++i2) {")
-    w("      const FxPrimPair bra = pab[i1 * Nt + i2];")
-    w("      const double p = bra.p, op = bra.op, Px = bra.Px, Py = bra.Py, Pz = bra.Pz;")
-    w("      for (int i3 = 0; i3 < x3.nprim; ++i3) {")
-    w("        for (int i4 = 0; i4 < x4.nprim; ++i4) {")
-    w("          const FxPrimPair ket = pcd[i3 * Nt + i4];")
-    w("          const double q = ket.p, oq = ket.op, Qx = ket.Px, Qy = ket.Py, Qz = ket.Pz;")
-    w("          const double ppq = p + q, oppq = 1.0 / ppq, rho = p * q * oppq;")
-    w("          const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;")
-    w("          const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);")
-    w("          const double pref = FX_TWO_PI_POW_2_5 * op * oq * sqrt(oppq) * bra.K * ket.K;")
-    w(f"          double F[{Lsum + 1}];")
-    w(f"          fx_boys<{Lsum}>(T, boys_tab, F);")
+    # the primitive-quartet body, instantiated twice: the first primitive
+    # quartet stores into X, the others add to it
+    w("  auto prim = [&](int i1, int i2, int i3, int i4, auto acc) {")
+    w("    constexpr bool ACC = decltype(acc)::value;")
+    w("    const FxPrimPair bra = pab[i1 * Nt + i2];")
+    w("    const double p = bra.p, op = bra.op, Px = bra.Px, Py = bra.Py, Pz = bra.Pz;")
+    w("    const FxPrimPair ket = pcd[i3 * Nt + i4];")
+    w("    const double q = ket.p, oq = ket.op, Qx = ket.Px, Qy = ket.Py, Qz = ket.Pz;")
+    w("    const double ppq = p + q, oppq = 1.0 / ppq, rho = p * q * oppq;")
+    w("    const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;")
+    w("    const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);")
+    w("    const double pref = FX_TWO_PI_POW_2_5 * op * oq * sqrt(oppq) * bra.K * ket.K;")
+    w(f"    double F[{Lsum + 1}];")
+    w(f"    fx_boys<{Lsum}>(T, boys_tab, F);")
     for m in range(Lsum + 1):
-        w(f"          const {real} s{m} = ({real})(pref * F[{m}]);")
-    w("          const double Wx = (p * Px + q * Qx) * oppq, Wy = (p * Py + q * Qy) * oppq, Wz = (p * Pz + q * Qz) * oppq;")
+        w(f"    const {real} s{m} = ({real})(pref * F[{m}]);")
+    w("    const double Wx = (p * Px + q * Qx) * oppq, Wy = (p * Py + q * Qy) * oppq, Wz = (p * Pz + q * Qz) * oppq;")
     for c in "xyz":
-        w(f"          const {real} PA{c} = ({real})(P{c} - x1.{c}), WP{c} = ({real})(W{c} - P{c});")
-        w(f"          const {real} QC{c} = ({real})(Q{c} - x3.{c}), WQ{c} = ({real})(W{c} - Q{c});")
-    w(f"          const {real} oo2p = ({real})(0.5 * op), oo2q = ({real})(0.5 * oq), oo2pq = ({real})(0.5 * oppq);")
-    w(f"          const {real} oo2p_rp = ({real})(0.5 * op * rho * op), oo2q_rq = ({real})(0.5 * oq * rho * oq);")
-    w("          (void)PAx; (void)PAy; (void)PAz; (void)WPx; (void)WPy; (void)WPz;")
-    w("          (void)QCx; (void)QCy; (void)QCz; (void)WQx; (void)WQy; (void)WQz;")
-    w("          (void)oo2p; (void)oo2q; (void)oo2pq; (void)oo2p_rp; (void)oo2q_rq;")
+        w(f"    const {real} PA{c} = ({real})(P{c} - x1.{c}), WP{c} = ({real})(W{c} - P{c});")
+        w(f"    const {real} QC{c} = ({real})(Q{c} - x3.{c}), WQ{c} = ({real})(W{c} - Q{c});")
+    w(f"    const {real} oo2p = ({real})(0.5 * op), oo2q = ({real})(0.5 * oq), oo2pq = ({real})(0.5 * oppq);")
+    w(f"    const {real} oo2p_rp = ({real})(0.5 * op * rho * op), oo2q_rq = ({real})(0.5 * oq * rho * oq);")
+    w("    (void)PAx; (void)PAy; (void)PAz; (void)WPx; (void)WPy; (void)WPz;")
+    w("    (void)QCx; (void)QCy; (void)QCz; (void)WQx; (void)WQy; (void)WQz;")
+    w("    (void)oo2p; (void)oo2q; (void)oo2pq; (void)oo2p_rp; (void)oo2q_rq;")
     # store each target right after the statement that forms it
     tpos = {nm: k for k, nm in enumerate(tnames)}
-    zero = "0.0f" if real == "float" else "0.0"
     for line in vem.lines:
-        w("          " + line)
+        w("    " + line)
         nm = line.split(" = ", 1)[0].split()[-1]
         if nm in tpos:
             k = tpos.pop(nm)
-            w(f"          X[{k}] = (first ? {zero} : X[{k}]) + {nm};")
+            w(f"    if constexpr (ACC) X[{k}] += {nm}; else X[{k}] = {nm};")
     for nm, k in tpos.items():     # targets that are base values s_m
-        w(f"          X[{k}] = (first ? {zero} : X[{k}]) + {nm};")
-    w("          first = false;")
-    w("        }")
-    w("      }")
-    w("    }")
-    w("  }")
+        w(f"    if constexpr (ACC) X[{k}] += {nm}; else X[{k}] = {nm};")
+    w("  };")
+    w("  prim(0, 0, 0, 0, FxAcc<false>{});")
+    w("  for (int i1 = 0; i1 < x1.nprim; ++i1)")
+    w("    for (int i2 = 0; i2 < x2.nprim; ++i2)")
+    w("      for (int i3 = 0; i3 < x3.nprim; ++i3)")
+    w("        for (int i4 = 0; i4 < x4.nprim; ++i4)")
+    w("          if (i1 | i2 | i3 | i4) prim(i1, i2, i3, i4, FxAcc<true>{});")
     w(f"  const {real} ABx_ = ({real})ABx, ABy_ = ({real})ABy, ABz_ = ({real})ABz;")
     w(f"  const {real} CDx_ = ({real})CDx, CDy_ = ({real})CDy, CDz_ = ({real})CDz;")
     w("  (void)ABx_; (void)ABy_; (void)ABz_; (void)CDx_; (void)CDy_; (void)CDz_;")
@@ -568,11 +568,17 @@ COOP_MIN, THREAD_MAX = 100, 1 << 30
 
 
 # Waves per SIMD that the register allocation of a one-quartet-per-lane
-# kernel must allow (default 1, i.e. up to 512 registers per lane).  Set from
-# measurement on the 1000-atom s+p+d cluster: only the (dd|dd) FP64 kernel,
-# which spills 15 KB per lane at one wave, ran faster at two (-21%); every
-# other spilling kernel ran as fast or slower.
-MIN_WAVES = {("dddd", "f64"): 2}
+# kernel must allow (default 1, i.e. up to 512 registers per lane).  On the
+# 1000-atom s+p+d cluster two waves made only the register form of (dd|dd)
+# FP64 faster (-21%), which the staged form below beats (-49%).
+MIN_WAVES = {}
+
+# (class, precision) pairs whose one-quartet-per-lane routine is the staged
+# form (gen_class_staged).
+# Chosen by measurement on the 1000-atom s+p+d cluster: the staged form was
+# faster only where the register form spills most (three or four d shells in
+# FP64, (dd|dd) in FP32), by 25-49%, and slower elsewhere.
+STAGED = {("dddd", "f64"), ("dddd", "f32"), ("dddp", "f64"), ("ddpd", "f64"), ("pddd", "f64"), ("dpdd", "f64")}
 
 
 def variants(la, lb, lc, ld):
@@ -590,6 +596,8 @@ def main(outdir):
         parts = []
         for real in ("double", "float"):
             code, fp, fc = gen_class(la, lb, lc, ld, real)
+            if (cls, "f32" if real == "float" else "f64") in STAGED:
+                code = gen_class_staged(la, lb, lc, ld, real)[0]
             if th:
                 parts.append(code)
             if real == "double":

@@ -410,3 +410,20 @@ def test_atom_permutation_permutes_K(cube10):
                 np.arange(len(order), dtype=np.int32), s.P[np.ix_(fperm, fperm)], s.tau)
     K2, _ = oracle.exchange(s2, tau=1e-7)
     assert np.abs(K2 - K[np.ix_(fperm, fperm)]).max() < 1e-13 * np.abs(K).max()
+
+
+def test_density_block_norms_match_numpy(spd):
+    """Eq. (8) density factor: Pn_bc = max(||P_bc||_F, ||P_cb||_F) over the
+    shell blocks, against numpy's Frobenius norm on a non-symmetric P."""
+    s = spd[0]
+    rng = np.random.default_rng(9)
+    P = rng.standard_normal((s.nbf, s.nbf))
+    Pn = oracle.pnorm(s, P)
+    off = np.concatenate([[0], np.cumsum([(l + 1) * (l + 2) // 2 for l in s.l])])
+    for b in range(s.nshell):
+        for c in range(s.nshell):
+            blk = P[off[b]:off[b + 1], off[c]:off[c + 1]]
+            blkT = P[off[c]:off[c + 1], off[b]:off[b + 1]]
+            ref = max(np.linalg.norm(blk), np.linalg.norm(blkT))
+            assert abs(Pn[b, c] - ref) <= 1e-14 * ref
+    assert np.array_equal(Pn, Pn.T)
