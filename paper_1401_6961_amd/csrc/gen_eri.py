@@ -575,10 +575,14 @@ MIN_WAVES = {}
 
 # (class, precision) pairs whose one-quartet-per-lane routine is the staged
 # form (gen_class_staged).
-# Chosen by measurement on the 1000-atom s+p+d cluster: the staged form was
-# faster only where the register form spills most (three or four d shells in
-# FP64, (dd|dd) in FP32), by 25-49%, and slower elsewhere.
-STAGED = {("dddd", "f64"), ("dddd", "f32"), ("dddp", "f64"), ("ddpd", "f64"), ("pddd", "f64"), ("dpdd", "f64")}
+# Chosen per kernel by measurement on the 1000-atom s+p+d cluster (both forms
+# built for 19 classes, the faster kept): the staged form wins wherever the
+# register form spills kilobytes per lane -- every FP64 class with two or more
+# d shells, and FP32 with three or four -- and loses where it spills little
+# or nothing (FP32 with two d shells, all (pp|pd)-type classes).
+STAGED = {(c, "f64") for c in ("sddd", "ppdd", "pdpd", "pddp", "pddd", "dsdd", "dppd", "dpdp", "dpdd", "ddsd", "ddpp",
+                               "ddpd", "ddds", "dddp", "dddd")} | \
+         {(c, "f32") for c in ("pddd", "dpdd", "ddpd", "dddp", "dddd")}
 
 
 def variants(la, lb, lc, ld):
