@@ -568,9 +568,9 @@ COOP_MIN, THREAD_MAX = 100, 1 << 30
 
 
 # Waves per SIMD that the register allocation of a one-quartet-per-lane
-# kernel must allow (default 1, i.e. up to 512 registers per lane).  On the
-# 1000-atom s+p+d cluster two waves made only the register form of (dd|dd)
-# FP64 faster (-21%), which the staged form below beats (-49%).
+# kernel must allow (default 1, i.e. up to 512 registers per lane; set below
+# for some staged kernels).  Of the register-form kernels only (dd|dd) FP64
+# ran faster at two waves (-21%), and its staged form beats that.
 MIN_WAVES = {}
 
 # (class, precision) pairs whose one-quartet-per-lane routine is the staged
@@ -583,6 +583,10 @@ MIN_WAVES = {}
 STAGED = {(c, "f64") for c in ("sddd", "ppdd", "pdpd", "pddp", "pddd", "dsdd", "dppd", "dpdp", "dpdd", "ddsd", "ddpp",
                                "ddpd", "ddds", "dddp", "dddd")} | \
          {(c, "f32") for c in ("pddd", "dpdd", "ddpd", "dddp", "dddd")}
+# Staged kernels measured at one and at two waves per SIMD (1000-atom
+# cluster); two kept where they were at least 3% faster.
+MIN_WAVES = {(c, "f64"): 2 for c in ("dddd", "ddds", "ddsd", "dsdd", "sddd", "ddpp", "dddp", "ddpd", "pddd", "dpdd",
+                                     "ppdd")} | {("dddp", "f32"): 2, ("pddd", "f32"): 2}
 
 
 def variants(la, lb, lc, ld):
