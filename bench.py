@@ -37,21 +37,28 @@ def cname(c):
     return f"({LNAME[c // 27]}{LNAME[(c // 9) % 3]}|{LNAME[(c // 3) % 3]}{LNAME[c % 3]})"
 
 
-GEN_SOURCES = ("paper_1401_6961_amd/csrc/gen_eri.py", "paper_1401_6961_amd/csrc/fx_eri_common.h",
-               "paper_1401_6961_amd/csrc/fx_internal.h")
+def kernel_sources_hash(kernel):
+    """Hash of the sources a class kernel is compiled from: its generated
+    class file and the shared kernel templates (None if one is missing)."""
+    import hashlib
+    cls = kernel[len("fx_k_"):len("fx_k_") + 4]
+    h = hashlib.sha256()
+    for p in (f"paper_1401_6961_amd/csrc/gen/eri_{cls}.hip", "paper_1401_6961_amd/csrc/fx_eri_common.h",
+              "paper_1401_6961_amd/csrc/fx_internal.h"):
+        path = os.path.join(ROOT, p)
+        if not os.path.exists(path):
+            return None
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def profiled_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (profiles/hbm_traffic_*.md), provided the kernel sources hash to
+    summary (profiles/hbm_traffic_*.md), provided the kernel's sources hash to
     the value recorded with the counters; (None, None) otherwise."""
     import glob
-    import hashlib
     import re
-    h = hashlib.sha256()
-    for p in GEN_SOURCES:
-        h.update(open(os.path.join(ROOT, p), "rb").read())
-    gh = h.hexdigest()[:16]
+    gh = kernel_sources_hash(kernel)
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md"))):
         m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
         if not m:

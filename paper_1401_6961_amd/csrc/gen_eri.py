@@ -584,7 +584,9 @@ STAGED = {(c, "f64") for c in ("sddd", "ppdd", "pdpd", "pddp", "pddd", "dsdd", "
                                "ddpd", "ddds", "dddp", "dddd")} | \
          {(c, "f32") for c in ("pddd", "dpdd", "ddpd", "dddp", "dddd")}
 # Staged kernels measured at one and at two waves per SIMD (1000-atom
-# cluster); two kept where they were at least 3% faster.
+# cluster); two kept where they were at least 3% faster.  Forcing three or
+# four waves on register-form kernels that fit at one or two made them spill
+# and run about three times slower.
 MIN_WAVES = {(c, "f64"): 2 for c in ("dddd", "ddds", "ddsd", "dsdd", "sddd", "ddpp", "dddp", "ddpd", "pddd", "dpdd",
                                      "ppdd")} | {("dddp", "f32"): 2, ("pddd", "f32"): 2}
 
