@@ -29,6 +29,7 @@ per contracted quartet, which the library reports as algorithmic flops.
 from __future__ import annotations
 
 import itertools
+import re
 import os
 import sys
 
@@ -376,7 +377,7 @@ def gen_class(la, lb, lc, ld, real, diag=False):
     return "\n".join(out), vem.flops, hem.flops + cflops
 
 
-def gen_class_staged(la, lb, lc, ld, real):
+def gen_class_staged(la, lb, lc, ld, real, paired=False):
     """Staged form of the same routine, for classes whose [e0|f0] block does
     not fit in registers.  Same arithmetic, different data movement: the
     accumulated [e0|f0] block X and the bra-transferred block Y = (x1 x2|f)
@@ -385,7 +386,9 @@ def gen_class_staged(la, lb, lc, ld, real):
     quartet and read once:
 
       1. per primitive quartet: Boys, VRR; every target [e0|f0] is added
-         into X as soon as it is formed;
+         into X as soon as it is formed (with `paired`, two primitive
+         quartets are evaluated side by side and X is updated once per
+         pair);
       2. bra HRR one ket column f at a time: read X[., f], write Y[., f];
       3. ket HRR one bra row at a time: read Y[row, .], form the row's
          integrals and contract each into kacc at once.
@@ -426,48 +429,93 @@ def gen_class_staged(la, lb, lc, ld, real):
     w("  const long Nt = B.ntprim;")
     w("  const FxPrimPair* __restrict__ pab = B.pp + (long)x1.pofs * Nt + x2.pofs;")
     w("  const FxPrimPair* __restrict__ pcd = B.pp + (long)x3.pofs * Nt + x4.pofs;")
-    # the primitive-quartet body, instantiated twice: the first primitive
-    # quartet stores into X, the others add to it
-    w("  auto prim = [&](int i1, int i2, int i3, int i4, auto acc) {")
-    w("    constexpr bool ACC = decltype(acc)::value;")
-    w("    const FxPrimPair bra = pab[i1 * Nt + i2];")
-    w("    const double p = bra.p, op = bra.op, Px = bra.Px, Py = bra.Py, Pz = bra.Pz;")
-    w("    const FxPrimPair ket = pcd[i3 * Nt + i4];")
-    w("    const double q = ket.p, oq = ket.op, Qx = ket.Px, Qy = ket.Py, Qz = ket.Pz;")
-    w("    const double ppq = p + q, oppq = 1.0 / ppq, rho = p * q * oppq;")
-    w("    const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;")
-    w("    const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);")
-    w("    const double pref = FX_TWO_PI_POW_2_5 * op * oq * sqrt(oppq) * bra.K * ket.K;")
-    w(f"    double F[{Lsum + 1}];")
-    w(f"    fx_boys<{Lsum}>(T, boys_tab, F);")
-    for m in range(Lsum + 1):
-        w(f"    const {real} s{m} = ({real})(pref * F[{m}]);")
-    w("    const double Wx = (p * Px + q * Qx) * oppq, Wy = (p * Py + q * Qy) * oppq, Wz = (p * Pz + q * Qz) * oppq;")
-    for c in "xyz":
-        w(f"    const {real} PA{c} = ({real})(P{c} - x1.{c}), WP{c} = ({real})(W{c} - P{c});")
-        w(f"    const {real} QC{c} = ({real})(Q{c} - x3.{c}), WQ{c} = ({real})(W{c} - Q{c});")
-    w(f"    const {real} oo2p = ({real})(0.5 * op), oo2q = ({real})(0.5 * oq), oo2pq = ({real})(0.5 * oppq);")
-    w(f"    const {real} oo2p_rp = ({real})(0.5 * op * rho * op), oo2q_rq = ({real})(0.5 * oq * rho * oq);")
-    w("    (void)PAx; (void)PAy; (void)PAz; (void)WPx; (void)WPy; (void)WPz;")
-    w("    (void)QCx; (void)QCy; (void)QCz; (void)WQx; (void)WQy; (void)WQz;")
-    w("    (void)oo2p; (void)oo2q; (void)oo2pq; (void)oo2p_rp; (void)oo2q_rq;")
-    # store each target right after the statement that forms it
-    tpos = {nm: k for k, nm in enumerate(tnames)}
-    for line in vem.lines:
-        w("    " + line)
-        nm = line.split(" = ", 1)[0].split()[-1]
-        if nm in tpos:
+    tpos0 = {nm: k for k, nm in enumerate(tnames)}
+
+    def setup(j, ind, wexpr=None):
+        """Set-up of primitive quartet j (names suffixed _j); `wexpr`
+        scales its prefactor (0 for a padding quartet)."""
+        sfx = f"_{j}"
+        w(f"{ind}const FxPrimPair bra{sfx} = pab[i1{sfx} * Nt + i2{sfx}];")
+        w(f"{ind}const double p{sfx} = bra{sfx}.p, op{sfx} = bra{sfx}.op, Px{sfx} = bra{sfx}.Px, Py{sfx} = bra{sfx}.Py, "
+          f"Pz{sfx} = bra{sfx}.Pz;")
+        w(f"{ind}const FxPrimPair ket{sfx} = pcd[i3{sfx} * Nt + i4{sfx}];")
+        w(f"{ind}const double q{sfx} = ket{sfx}.p, oq{sfx} = ket{sfx}.op, Qx{sfx} = ket{sfx}.Px, Qy{sfx} = ket{sfx}.Py, "
+          f"Qz{sfx} = ket{sfx}.Pz;")
+        w(f"{ind}const double ppq{sfx} = p{sfx} + q{sfx}, oppq{sfx} = 1.0 / ppq{sfx}, rho{sfx} = p{sfx} * q{sfx} * oppq{sfx};")
+        w(f"{ind}const double PQx{sfx} = Px{sfx} - Qx{sfx}, PQy{sfx} = Py{sfx} - Qy{sfx}, PQz{sfx} = Pz{sfx} - Qz{sfx};")
+        w(f"{ind}const double T{sfx} = rho{sfx} * (PQx{sfx} * PQx{sfx} + PQy{sfx} * PQy{sfx} + PQz{sfx} * PQz{sfx});")
+        scale = f" * {wexpr}" if wexpr else ""
+        w(f"{ind}const double pref{sfx} = FX_TWO_PI_POW_2_5 * op{sfx} * oq{sfx} * sqrt(oppq{sfx}) * bra{sfx}.K * "
+          f"ket{sfx}.K{scale};")
+        w(f"{ind}double F{sfx}[{Lsum + 1}];")
+        w(f"{ind}fx_boys<{Lsum}>(T{sfx}, boys_tab, F{sfx});")
+        for m in range(Lsum + 1):
+            w(f"{ind}const {real} s{m}{sfx} = ({real})(pref{sfx} * F{sfx}[{m}]);")
+        w(f"{ind}const double Wx{sfx} = (p{sfx} * Px{sfx} + q{sfx} * Qx{sfx}) * oppq{sfx}, "
+          f"Wy{sfx} = (p{sfx} * Py{sfx} + q{sfx} * Qy{sfx}) * oppq{sfx}, Wz{sfx} = (p{sfx} * Pz{sfx} + q{sfx} * Qz{sfx}) * oppq{sfx};")
+        for c in "xyz":
+            w(f"{ind}const {real} PA{c}{sfx} = ({real})(P{c}{sfx} - x1.{c}), WP{c}{sfx} = ({real})(W{c}{sfx} - P{c}{sfx});")
+            w(f"{ind}const {real} QC{c}{sfx} = ({real})(Q{c}{sfx} - x3.{c}), WQ{c}{sfx} = ({real})(W{c}{sfx} - Q{c}{sfx});")
+        w(f"{ind}const {real} oo2p{sfx} = ({real})(0.5 * op{sfx}), oo2q{sfx} = ({real})(0.5 * oq{sfx}), "
+          f"oo2pq{sfx} = ({real})(0.5 * oppq{sfx});")
+        w(f"{ind}const {real} oo2p_rp{sfx} = ({real})(0.5 * op{sfx} * rho{sfx} * op{sfx}), "
+          f"oo2q_rq{sfx} = ({real})(0.5 * oq{sfx} * rho{sfx} * oq{sfx});")
+        for nm in ("PAx", "PAy", "PAz", "WPx", "WPy", "WPz", "QCx", "QCy", "QCz", "WQx", "WQy", "WQz", "oo2p", "oo2q",
+                   "oo2pq", "oo2p_rp", "oo2q_rq"):
+            w(f"{ind}(void){nm}{sfx};")
+
+    tok = re.compile(r"\b(v\d+|s\d+|PA[xyz]|WP[xyz]|QC[xyz]|WQ[xyz]|oo2p|oo2q|oo2pq|oo2p_rp|oo2q_rq)\b")
+
+    def vrr_lines(nj, ind):
+        """The VRR of nj primitive quartets, interleaved node by node; each
+        target goes into X (store, or add when ACC) as soon as all nj
+        copies of it are formed."""
+        tpos = dict(tpos0)
+
+        def put(nm):
             k = tpos.pop(nm)
-            w(f"    if constexpr (ACC) X[{k}] += {nm}; else X[{k}] = {nm};")
-    for nm, k in tpos.items():     # targets that are base values s_m
-        w(f"    if constexpr (ACC) X[{k}] += {nm}; else X[{k}] = {nm};")
-    w("  };")
-    w("  prim(0, 0, 0, 0, FxAcc<false>{});")
-    w("  for (int i1 = 0; i1 < x1.nprim; ++i1)")
-    w("    for (int i2 = 0; i2 < x2.nprim; ++i2)")
-    w("      for (int i3 = 0; i3 < x3.nprim; ++i3)")
-    w("        for (int i4 = 0; i4 < x4.nprim; ++i4)")
-    w("          if (i1 | i2 | i3 | i4) prim(i1, i2, i3, i4, FxAcc<true>{});")
+            sm = " + ".join(f"{nm}_{j}" for j in range(nj))
+            w(f"{ind}if constexpr (ACC) X[{k}] += {sm}; else X[{k}] = {sm};")
+        for line in vem.lines:
+            for j in range(nj):
+                w(ind + tok.sub(lambda m: m.group(1) + f"_{j}", line))
+            nm = line.split(" = ", 1)[0].split()[-1]
+            if nm in tpos:
+                put(nm)
+        for nm in list(tpos):          # targets that are base values s_m
+            put(nm)
+
+    if paired:
+        # two primitive quartets per pass (the second of an odd count is a
+        # zero-weight copy of the last): one X update per target and pass
+        w("  const int n4 = x4.nprim, n34 = x3.nprim * n4, n234 = x2.nprim * n34;")
+        w("  const int nq = x1.nprim * n234;")
+        w("  auto prim2 = [&](int qa, int qb, double wb, auto acc) {")
+        w("    constexpr bool ACC = decltype(acc)::value;")
+        for j, qv in ((0, "qa"), (1, "qb")):
+            w(f"    const int i1_{j} = {qv} / n234, i2_{j} = ({qv} / n34) % x2.nprim, i3_{j} = ({qv} / n4) % x3.nprim, "
+              f"i4_{j} = {qv} % n4;")
+        setup(0, "    ")
+        setup(1, "    ", "wb")
+        vrr_lines(2, "    ")
+        w("  };")
+        w("  prim2(0, nq > 1 ? 1 : 0, nq > 1 ? 1.0 : 0.0, FxAcc<false>{});")
+        w("  for (int q = 2; q < nq; q += 2)")
+        w("    prim2(q, q + 1 < nq ? q + 1 : q, q + 1 < nq ? 1.0 : 0.0, FxAcc<true>{});")
+    else:
+        # the primitive-quartet body, instantiated twice: the first primitive
+        # quartet stores into X, the others add to it
+        w("  auto prim = [&](int i1_0, int i2_0, int i3_0, int i4_0, auto acc) {")
+        w("    constexpr bool ACC = decltype(acc)::value;")
+        setup(0, "    ")
+        vrr_lines(1, "    ")
+        w("  };")
+        w("  prim(0, 0, 0, 0, FxAcc<false>{});")
+        w("  for (int i1 = 0; i1 < x1.nprim; ++i1)")
+        w("    for (int i2 = 0; i2 < x2.nprim; ++i2)")
+        w("      for (int i3 = 0; i3 < x3.nprim; ++i3)")
+        w("        for (int i4 = 0; i4 < x4.nprim; ++i4)")
+        w("          if (i1 | i2 | i3 | i4) prim(i1, i2, i3, i4, FxAcc<true>{});")
     w(f"  const {real} ABx_ = ({real})ABx, ABy_ = ({real})ABy, ABz_ = ({real})ABz;")
     w(f"  const {real} CDx_ = ({real})CDx, CDy_ = ({real})CDy, CDz_ = ({real})CDz;")
     w("  (void)ABx_; (void)ABy_; (void)ABz_; (void)CDx_; (void)CDy_; (void)CDz_;")
@@ -583,12 +631,19 @@ MIN_WAVES = {}
 STAGED = {(c, "f64") for c in ("sddd", "ppdd", "pdpd", "pddp", "pddd", "dsdd", "dppd", "dpdp", "dpdd", "ddsd", "ddpp",
                                "ddpd", "ddds", "dddp", "dddd")} | \
          {(c, "f32") for c in ("pddd", "dpdd", "ddpd", "dddp", "dddd")}
-# Staged kernels measured at one and at two waves per SIMD (1000-atom
-# cluster); two kept where they were at least 3% faster.  Forcing three or
-# four waves on register-form kernels that fit at one or two made them spill
-# and run about three times slower.
-MIN_WAVES = {(c, "f64"): 2 for c in ("dddd", "ddds", "ddsd", "dsdd", "sddd", "ddpp", "dddp", "ddpd", "pddd", "dpdd",
-                                     "ppdd")} | {("dddp", "f32"): 2, ("pddd", "f32"): 2}
+# Staged classes evaluated one primitive quartet per pass: (dd|dd) has a
+# single primitive quartet in the usual bases, and for the classes with an s
+# shell (three primitives) the zero-weight padding of an odd count cost more
+# than pairing saved (measured +10-25%); pairing saved 4-20% elsewhere.
+UNPAIRED = {"dddd", "ddds", "ddsd", "dsdd", "sddd"}
+
+# Staged kernels measured at one, two and three waves per SIMD (1000-atom
+# cluster); the fastest kept where it was at least 3% faster than one wave.
+# Forcing three or four waves on register-form kernels that fit at one or
+# two made them spill and run about three times slower.
+MIN_WAVES = {(c, "f64"): 2 for c in ("ddds", "ddsd", "dsdd", "sddd", "ddpp", "ppdd")} | \
+            {(c, "f64"): 3 for c in ("dddd", "dddp", "ddpd", "dpdd", "pddd")} | \
+            {("dddp", "f32"): 3, ("pddd", "f32"): 3}
 
 
 def variants(la, lb, lc, ld):
@@ -607,7 +662,7 @@ def main(outdir):
         for real in ("double", "float"):
             code, fp, fc = gen_class(la, lb, lc, ld, real)
             if (cls, "f32" if real == "float" else "f64") in STAGED:
-                code = gen_class_staged(la, lb, lc, ld, real)[0]
+                code = gen_class_staged(la, lb, lc, ld, real, paired=cls not in UNPAIRED)[0]
             if th:
                 parts.append(code)
             if real == "double":
