@@ -29,6 +29,7 @@ per contracted quartet, which the library reports as algorithmic flops.
 from __future__ import annotations
 
 import itertools
+import math
 import re
 import os
 import sys
@@ -377,7 +378,82 @@ def gen_class(la, lb, lc, ld, real, diag=False):
     return "\n".join(out), vem.flops, hem.flops + cflops
 
 
-def gen_class_staged(la, lb, lc, ld, real, paired=False):
+def _emit_fold(w, real, o, comps, icomp, fcols, idx):
+    """Steps 2+3 of the folded staged routine: per ket column f, the bra HRR
+    of X[., f] into registers, then every (x3 x4) component whose closed-form
+    ket HRR uses column f adds (x1 x2|f) * coef * P into kacc."""
+    fl = 0
+    nd = len(comps[3])
+    index = [{t: k for k, t in enumerate(comps[r])} for r in range(4)]
+    for jn, nu in enumerate(comps[1]):
+        for kl, lam in enumerate(comps[2]):
+            fac = comp_factor(nu) * comp_factor(lam)
+            if abs(fac - 1.0) < 1e-15:
+                w(f"  const double pv{jn}_{kl} = Pmat[{jn} * ldp + {kl}];")
+            else:
+                w(f"  const double pv{jn}_{kl} = Pmat[{jn} * ldp + {kl}] * {fac!r};")
+                fl += 1
+    w("  const double CDx2 = CDx * CDx, CDy2 = CDy * CDy, CDz2 = CDz * CDz;")
+    w("  (void)CDx2; (void)CDy2; (void)CDz2;")
+    powname = {1: "CD{}", 2: "CD{}2"}
+    for f in fcols:
+        hem = Emitter(real)
+        loads = {}
+
+        def xval(e, f_, hem=hem, loads=loads):
+            k = idx[(e, f_)]
+            if k not in loads:
+                nm = hem.new("x")
+                hem.emit(f"const {real} {nm} = X[{k}];")
+                loads[k] = nm
+            return loads[k]
+        hrr = HRR(hem, xval)
+        yf = {}
+        for t1 in icomp[0]:
+            for t2 in icomp[1]:
+                yf[(t1, t2)] = hrr.bra(t1, t2, f)
+        w("  {")
+        for line in hem.lines:
+            w("    " + line)
+        fl += hem.flops
+        nu_ = 0
+        for t3 in icomp[2]:
+            for t4 in icomp[3]:
+                k = tuple(f[i] - t3[i] for i in range(3))
+                if any(k[i] < 0 or k[i] > t4[i] for i in range(3)):
+                    continue
+                fac = 1
+                parts = []
+                for i in range(3):
+                    fac *= math.comb(t4[i], k[i])
+                    pw = t4[i] - k[i]
+                    if pw:
+                        parts.append(powname[pw].format(XYZ[i]))
+                coef = " * ".join(([f"{fac}.0"] if fac != 1 else []) + parts)
+                # one FP64 factor coef * P per distinct density element
+                us = {}
+                for t1 in icomp[0]:
+                    for t2 in icomp[1]:
+                        ext = [None] * 4
+                        for pos, role in enumerate(o):
+                            ext[role] = (t1, t2, t3, t4)[pos]
+                        im, jn, kl, ls_ = (index[r][ext[r]] for r in range(4))
+                        key = (jn, kl)
+                        if key not in us:
+                            if coef:
+                                nu_ += 1
+                                us[key] = f"u{nu_}"
+                                w(f"    const double u{nu_} = {coef} * pv{jn}_{kl};")
+                                fl += 1 + len(parts) + (fac != 1)
+                            else:
+                                us[key] = f"pv{jn}_{kl}"
+                        w(f"    kacc[{im * nd + ls_}] += (double){yf[(t1, t2)]} * {us[key]};")
+                        fl += 2
+        w("  }")
+    return fl
+
+
+def gen_class_staged(la, lb, lc, ld, real, paired=False, fold=False):
     """Staged form of the same routine, for classes whose [e0|f0] block does
     not fit in registers.  Same arithmetic, different data movement: the
     accumulated [e0|f0] block X and the bra-transferred block Y = (x1 x2|f)
@@ -392,6 +468,12 @@ def gen_class_staged(la, lb, lc, ld, real, paired=False):
       2. bra HRR one ket column f at a time: read X[., f], write Y[., f];
       3. ket HRR one bra row at a time: read Y[row, .], form the row's
          integrals and contract each into kacc at once.
+
+    With `fold`, steps 2 and 3 become one pass over the ket columns and Y is
+    not formed: the ket HRR has the closed form
+      (x3, x4| = sum_{k <= x4} prod_i C(x4_i, k_i) CD_i^(x4_i - k_i) (x3 + k, 0|,
+    so column f = x3 + k of the bra-transferred block contributes
+    (x1 x2|f) * coef * P to the K block directly, in FP64.
 
     Returns (code, flops_per_prim, flops_per_contracted) like gen_class."""
     ls = (la, lb, lc, ld)
@@ -420,10 +502,15 @@ def gen_class_staged(la, lb, lc, ld, real, paired=False):
     w(f"  const FxShellRef& x1 = {x[0]}; const FxShellRef& x2 = {x[1]}; const FxShellRef& x3 = {x[2]}; const FxShellRef& x4 = {x[3]};")
     # The asm statement hides the arrays' addresses from the optimiser, so
     # they stay in private memory instead of being promoted to registers.
-    w(f"  {real} Xs[{NX}], Ys[{NY}];")
-    w(f"  __attribute__((address_space(5))) {real}* X = (__attribute__((address_space(5))) {real}*)Xs;")
-    w(f"  __attribute__((address_space(5))) {real}* Y = (__attribute__((address_space(5))) {real}*)Ys;")
-    w("  asm volatile(\"\" : \"+v\"(X), \"+v\"(Y));")
+    if fold:
+        w(f"  {real} Xs[{NX}];")
+        w(f"  __attribute__((address_space(5))) {real}* X = (__attribute__((address_space(5))) {real}*)Xs;")
+        w("  asm volatile(\"\" : \"+v\"(X));")
+    else:
+        w(f"  {real} Xs[{NX}], Ys[{NY}];")
+        w(f"  __attribute__((address_space(5))) {real}* X = (__attribute__((address_space(5))) {real}*)Xs;")
+        w(f"  __attribute__((address_space(5))) {real}* Y = (__attribute__((address_space(5))) {real}*)Ys;")
+        w("  asm volatile(\"\" : \"+v\"(X), \"+v\"(Y));")
     w("  const double ABx = x1.x - x2.x, ABy = x1.y - x2.y, ABz = x1.z - x2.z;")
     w("  const double CDx = x3.x - x4.x, CDy = x3.y - x4.y, CDz = x3.z - x4.z;")
     w("  const long Nt = B.ntprim;")
@@ -521,6 +608,10 @@ def gen_class_staged(la, lb, lc, ld, real, paired=False):
     w("  (void)ABx_; (void)ABy_; (void)ABz_; (void)CDx_; (void)CDy_; (void)CDz_;")
     idx = {t: k for k, t in enumerate(targets)}
     hflops = 0
+    if fold:
+        hflops += _emit_fold(w, real, o, comps, icomp, fcols, idx)
+        w("}")
+        return "\n".join(out), vem.flops, hflops
     # 2. bra HRR per ket column
     for f in fcols:
         hem = Emitter(real)
@@ -637,13 +728,23 @@ STAGED = {(c, "f64") for c in ("sddd", "ppdd", "pdpd", "pddp", "pddd", "dsdd", "
 # than pairing saved (measured +10-25%); pairing saved 4-20% elsewhere.
 UNPAIRED = {"dddd", "ddds", "ddsd", "dsdd", "sddd"}
 
+# Staged kernels with the folded ket HRR (gen_class_staged(fold=True)):
+# 17-55% faster than forming the bra-transferred block in private memory,
+# except (dd|dd) FP32 (4% slower).
+FOLD = set(STAGED) - {("dddd", "f32")}
+# With the fold, three FP32 classes with two d shells gain too (4-12%); the
+# other FP32 classes with one or two d shells and the (pp|pd)-type classes
+# stay faster in the register form.
+STAGED |= {("ddpp", "f32"), ("dppd", "f32"), ("ppdd", "f32")}
+FOLD |= {("ddpp", "f32"), ("dppd", "f32"), ("ppdd", "f32")}
+
 # Staged kernels measured at one, two and three waves per SIMD (1000-atom
-# cluster); the fastest kept where it was at least 3% faster than one wave.
-# Forcing three or four waves on register-form kernels that fit at one or
-# two made them spill and run about three times slower.
-MIN_WAVES = {(c, "f64"): 2 for c in ("ddds", "ddsd", "dsdd", "sddd", "ddpp", "ppdd")} | \
-            {(c, "f64"): 3 for c in ("dddd", "dddp", "ddpd", "dpdd", "pddd")} | \
-            {("dddp", "f32"): 3, ("pddd", "f32"): 3}
+# cluster); the fastest kept.  With the folded ket HRR most run best at one
+# wave (they need ~250 registers); (dd|dd) FP64 and the FP64 classes with an s
+# shell run best at three and two.  Forcing three or four waves on
+# register-form kernels that fit at one or two made them spill and run
+# about three times slower.
+MIN_WAVES = {("dddd", "f64"): 3} | {(c, "f64"): 2 for c in ("ddds", "ddsd", "dsdd", "sddd")}
 
 
 def variants(la, lb, lc, ld):
@@ -662,7 +763,8 @@ def main(outdir):
         for real in ("double", "float"):
             code, fp, fc = gen_class(la, lb, lc, ld, real)
             if (cls, "f32" if real == "float" else "f64") in STAGED:
-                code = gen_class_staged(la, lb, lc, ld, real, paired=cls not in UNPAIRED)[0]
+                code = gen_class_staged(la, lb, lc, ld, real, paired=cls not in UNPAIRED,
+                                        fold=(cls, "f32" if real == "float" else "f64") in FOLD)[0]
             if th:
                 parts.append(code)
             if real == "double":
