@@ -100,10 +100,12 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison build")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="cluster", choices=["cluster", "batched", "slab-mlp", "copy-probe"],
+    ap.add_argument("--workload", default="cluster",
+                    choices=["cluster", "batched", "slab-mlp", "copy-probe", "scaling"],
                     help="cluster: the headline 1000-atom s+p+d build; batched: 64 clusters in one batched "
                          "call vs 64 sequential builds; slab-mlp: 4000-atom s+p slab, learned vs bound-only "
-                         "scheduling; copy-probe: one elementwise copy of 1 GiB, to scale HBM byte counters")
+                         "scheduling; copy-probe: one elementwise copy of 1 GiB, to scale HBM byte counters; "
+                         "scaling: K-build time of s+p+d clusters of 125..2000 atoms (onset of linear scaling)")
     ap.add_argument("--no-tuning", action="store_true", help="ignore the autotuned kernel table")
     ap.add_argument("--no-symmetry", action="store_true", help="build every K block (no use of K = K^T)")
     args = ap.parse_args()
@@ -127,6 +129,8 @@ def main():
         return bench_batched(args, log)
     if args.workload == "slab-mlp":
         return bench_slab_mlp(args, log)
+    if args.workload == "scaling":
+        return bench_scaling(args, log)
 
     log(f"bench: generating {args.natom}-atom s+p+d cluster")
     system = synthetic.cluster(args.natom)
@@ -238,6 +242,46 @@ def copy_probe():
     torch.mul(src, 1.0, out=dst)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe": True, "bytes_read": 8 * n, "bytes_written": 8 * n, "dispatches": 2}))
+
+
+def bench_scaling(args, log):
+    """K-build time against system size: s+p+d clusters at 0.1 atoms/A^3
+    (the benchmark's recipe, seeds 2000 + natom), tau = 1e-8, mixed
+    precision.  Reports time and quartets per size and the log-log slope
+    between consecutive sizes (1 = linear scaling)."""
+    import numpy as np
+    import torch
+    import synthetic
+    import paper_1401_6961_amd as fx
+    sizes = (125, 250, 500, 1000, 2000)
+    rows = []
+    for natom in sizes:
+        s = synthetic.cluster(natom, seed=2000 + natom)
+        tree = fx.build_quadtree_from(s)
+        P = torch.from_numpy(s.P).cuda()
+        K = torch.zeros_like(P)
+        opts = fx.make_opts(precision=fx.FX_PREC_MIXED)
+        fx.fx_exchange_ex(tree, P, s.tau, K, opts)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = fx.fx_exchange_ex(tree, P, s.tau, K, opts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        rows.append({"natom": natom, "nbf": s.nbf, "kbuild_s": el, "quartets": st["quartets_covered"],
+                     "quartets_evaluated": st["quartets"]})
+        log(f"bench: scaling {natom} atoms n={s.nbf}: {el:.3f} s, {st['quartets_covered']:.3e} quartets")
+        del tree, P, K
+        torch.cuda.empty_cache()
+    for a, b in zip(rows, rows[1:]):
+        b["slope_time"] = float(np.log(b["kbuild_s"] / a["kbuild_s"]) / np.log(b["natom"] / a["natom"]))
+        b["slope_quartets"] = float(np.log(b["quartets"] / a["quartets"]) / np.log(b["natom"] / a["natom"]))
+    last = rows[-1]
+    print(json.dumps({"metric": "K-build s vs size, s+p+d clusters 125..2000 atoms, tau=1e-8, mixed",
+                      "value": last["quartets"] / last["kbuild_s"], "unit": "quartets/s", "n_gpus": 1, "steps": 1,
+                      "warmup": 1, "ms_per_step": 1e3 * last["kbuild_s"], "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+                      "config": {"workload": "s+p+d clusters of 125, 250, 500, 1000, 2000 atoms at 0.1 atoms/A^3"},
+                      "series": rows}))
 
 
 def bench_batched(args, log):
