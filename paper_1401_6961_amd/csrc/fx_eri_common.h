@@ -336,11 +336,11 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
 
 #define FX_LAUNCH_THREAD(cls, prec)                                                                     \
     hipLaunchKernelGGL(fx_k_##cls##_##prec,                                                             \
-                       dim3(grid > 0 ? grid : (A.nunits + FX_CLASS_WAVES - 1) / FX_CLASS_WAVES),         \
+                       dim3((A.nunits + FX_CLASS_WAVES - 1) / FX_CLASS_WAVES),         \
                        dim3(64 * FX_CLASS_WAVES), 0, st, A)
 #define FX_LAUNCH_COOP(cls, prec)                                                                       \
     hipLaunchKernelGGL(fx_kc_##cls##_##prec,                                                            \
-                       dim3(grid > 0 ? grid : (A.nunits + FX_COOP_WAVES - 1) / FX_COOP_WAVES),           \
+                       dim3((A.nunits + FX_COOP_WAVES - 1) / FX_COOP_WAVES),           \
                        dim3(64 * FX_COOP_WAVES), 0, st, A)
 
 // Both variants; `variant` 0 = thread, 1 = cooperative.
@@ -349,7 +349,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
     FX_THREAD_KERNEL(la, lb, lc, ld, cls, f32)                                                          \
     FX_COOP_KERNEL(la, lb, lc, ld, cls, f64, double)                                                    \
     FX_COOP_KERNEL(la, lb, lc, ld, cls, f32, float)                                                     \
-    int fx_launch_##cls(int prec32, int variant, FxClassArgs A, int grid, hipStream_t st) {              \
+    int fx_launch_##cls(int prec32, int variant, FxClassArgs A, hipStream_t st) {              \
         if (variant == 1) {                                                                              \
             if (prec32) FX_LAUNCH_COOP(cls, f32); else FX_LAUNCH_COOP(cls, f64);                         \
             return 1;                                                                                    \
@@ -361,7 +361,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
 #define FX_DEFINE_CLASS_KERNELS_THREAD(la, lb, lc, ld, cls)                                             \
     FX_THREAD_KERNEL(la, lb, lc, ld, cls, f64)                                                          \
     FX_THREAD_KERNEL(la, lb, lc, ld, cls, f32)                                                          \
-    int fx_launch_##cls(int prec32, int, FxClassArgs A, int grid, hipStream_t st) {                      \
+    int fx_launch_##cls(int prec32, int, FxClassArgs A, hipStream_t st) {                                \
         if (prec32) FX_LAUNCH_THREAD(cls, f32); else FX_LAUNCH_THREAD(cls, f64);                         \
         return 0;                                                                                        \
     }
@@ -369,7 +369,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
 #define FX_DEFINE_CLASS_KERNELS_COOP(la, lb, lc, ld, cls)                                               \
     FX_COOP_KERNEL(la, lb, lc, ld, cls, f64, double)                                                    \
     FX_COOP_KERNEL(la, lb, lc, ld, cls, f32, float)                                                     \
-    int fx_launch_##cls(int prec32, int, FxClassArgs A, int grid, hipStream_t st) {                      \
+    int fx_launch_##cls(int prec32, int, FxClassArgs A, hipStream_t st) {                                \
         if (prec32) FX_LAUNCH_COOP(cls, f32); else FX_LAUNCH_COOP(cls, f64);                             \
         return 1;                                                                                        \
     }

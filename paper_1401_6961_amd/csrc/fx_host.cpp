@@ -692,12 +692,8 @@ static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
     const bool use_mlp = c.schedule == FX_SCHED_MLP && c.cm;
     const int nbins = 32;
     const bool graph = c.use_graph && !c.profile && !c.rec;
-    // Independent class launches run on several streams so that the tail of
-    // one launch overlaps the next (they write disjoint K slots); each stream
-    // has its own scheduling buffers.  Recording, graph capture: one stream.
-    const int nstr = (graph || c.rec) ? 1 : FX_CLASS_STREAMS;
-    struct Lane {
-        hipStream_t s = nullptr;
+    // scheduling buffers (features, predicted costs, bins, launch order)
+    struct Sched {
         float4* feat = nullptr;
         float* cost = nullptr;
         int* flags = nullptr;
@@ -706,43 +702,21 @@ static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
         int* order = nullptr;
         long* bpartial = nullptr;
         long* total = nullptr;
-    };
-    std::vector<Lane> lanes(nstr);
+    } ln;
     float* times = nullptr;
-    for (auto& ln : lanes) {
-        if (sched || c.rec) {
-            ln.feat = A.get<float4>(maxlist);
-            ln.cost = A.get<float>(maxlist);
-        }
-        if (sched) {
-            ln.flags = A.get<int>((size_t)nbins * maxlist);
-            ln.key = A.get<uint8_t>(maxlist);
-            ln.bpos = A.get<long>((size_t)nbins * maxlist + 1);
-            ln.order = A.get<int>(maxlist);
-            ln.bpartial = A.get<long>(fx_scan_tiles((long)nbins * maxlist));
-            ln.total = A.get<long>(1);
-        }
+    if (sched || c.rec) {
+        ln.feat = A.get<float4>(maxlist);
+        ln.cost = A.get<float>(maxlist);
+    }
+    if (sched) {
+        ln.flags = A.get<int>((size_t)nbins * maxlist);
+        ln.key = A.get<uint8_t>(maxlist);
+        ln.bpos = A.get<long>((size_t)nbins * maxlist + 1);
+        ln.order = A.get<int>(maxlist);
+        ln.bpartial = A.get<long>(fx_scan_tiles((long)nbins * maxlist));
+        ln.total = A.get<long>(1);
     }
     if (c.rec) times = A.get<float>(maxlist);
-    struct StreamSet {
-        std::vector<hipStream_t> s;
-        std::vector<hipEvent_t> e;
-        ~StreamSet() {
-            for (auto x : e) (void)hipEventDestroy(x);
-            for (auto x : s) (void)hipStreamDestroy(x);
-        }
-    } ss;
-    if (nstr > 1) {
-        hipEvent_t start;
-        FX_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
-        ss.e.push_back(start);
-        FX_HIP(hipEventRecord(start, st));
-        for (auto& ln : lanes) {
-            FX_HIP(hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking));
-            ss.s.push_back(ln.s);
-            FX_HIP(hipStreamWaitEvent(ln.s, start, 0));
-        }
-    }
     hipGraph_t gr = nullptr;
     // Capture on a library-owned stream (the caller's may be the legacy default
     // stream, which cannot be captured); the graph is then launched on `st`.
@@ -758,8 +732,6 @@ static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
         FX_HIP(hipStreamBeginCapture(cap.s, hipStreamCaptureModeThreadLocal));
         st = cap.s;
     }
-    if (nstr == 1) lanes[0].s = st;
-    int next_lane = 0;
     std::vector<float> hfeat, htime;
     FxClassArgs args{};
     args.boys = segs[0]->T->boys;
@@ -790,9 +762,7 @@ static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
                                   (float)fx_class_hrr_flops[cls] + 1.f);
                     args.order = nullptr;
                     args.times = nullptr;
-                    Lane& ln = lanes[next_lane];
-                    next_lane = (next_lane + 1) % nstr;
-                    hipStream_t ls = ln.s;
+                    hipStream_t ls = st;
                     if (ln.feat) {
                         long o = 0;
                         for (auto* g : segs) {
@@ -822,18 +792,17 @@ static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
                         args.slot_index = slot_index(c, lb, lc, pr);
                         args.counters = c.counters + (cls * 2 + pr) * 3;
                         args.flags = g_flags[cls][pr];
-                        const int grid = 0;
                         if (c.profile) {
                             // events on the stream the kernel is launched on
                             ExCtx::Timed t{cls * 2 + pr, nullptr, nullptr};
                             FX_HIP(hipEventCreate(&t.a));
                             FX_HIP(hipEventCreate(&t.b));
                             FX_HIP(hipEventRecord(t.a, ls));
-                            fx_class_table[cls](pr, g_variant[cls][pr], args, grid, ls);
+                            fx_class_table[cls](pr, g_variant[cls][pr], args, ls);
                             FX_HIP(hipEventRecord(t.b, ls));
                             c.timed.push_back(t);
                         } else {
-                            fx_class_table[cls](pr, g_variant[cls][pr], args, grid, ls);
+                            fx_class_table[cls](pr, g_variant[cls][pr], args, ls);
                         }
                         if (c.rec) {
                             const long n = args.nunits;
@@ -851,16 +820,6 @@ static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
                     }
                 }
         }
-    if (nstr > 1) {
-        // join: the caller's stream waits for every class stream
-        for (auto& ln : lanes) {
-            hipEvent_t done;
-            FX_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
-            ss.e.push_back(done);
-            FX_HIP(hipEventRecord(done, ln.s));
-            FX_HIP(hipStreamWaitEvent(st, done, 0));
-        }
-    }
     if (graph) {
         FX_HIP(hipStreamEndCapture(cap.s, &gr));
         st = launch_st;

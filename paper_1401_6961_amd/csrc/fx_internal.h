@@ -5,11 +5,6 @@
 
 #define FX_CLASS_WAVES 4          // waves (work units) per thread-variant workgroup
 #define FX_COOP_WAVES 2           // waves per cooperative-variant workgroup
-// Streams over which independent class launches are spread.  Kept at 1: a
-// run with 4 concurrent class streams ended in HSA_STATUS_ERROR_OUT_OF_RESOURCES
-// on a queue (the spilling d-class kernels need large per-queue scratch); the
-// multi-stream path stays switched off until that is understood.
-#define FX_CLASS_STREAMS 1
 
 // Boys table: row i holds F_j(T_i), j = 0..14 (highest m 8 + 6 Taylor terms),
 // then e^{-T_i} in column 15; T_i = i / 32, i = 0..FX_BOYS_NROW-1.
@@ -89,9 +84,9 @@ struct FxClassArgs {
     float* times;                     // per-unit wall-clock ticks (nullable; timing probes)
 };
 
-// returns the variant launched (0 thread, 1 cooperative); `grid` workgroups
-// for persistent launches, 0 = one wave per unit
-#define FX_DECLARE_LAUNCH(cls) int fx_launch_##cls(int prec32, int variant, FxClassArgs A, int grid, hipStream_t st);
-typedef int (*fx_class_launcher)(int, int, FxClassArgs, int, hipStream_t);
+// launches one wave per unit; returns the variant launched (0 one quartet
+// per lane, 1 one quartet per wave)
+#define FX_DECLARE_LAUNCH(cls) int fx_launch_##cls(int prec32, int variant, FxClassArgs A, hipStream_t st);
+typedef int (*fx_class_launcher)(int, int, FxClassArgs, hipStream_t);
 void fx_launch_schwarz(FxDevBasis B, const double* boys, const int2* pairs, long npairs, double* Qn,
                        hipStream_t st);
