@@ -378,6 +378,65 @@ def gen_class(la, lb, lc, ld, real, diag=False):
     return "\n".join(out), vem.flops, hem.flops + cflops
 
 
+def _emit_prim_setup(w, real, Lsum, j, ind, wexpr=None):
+    """Set-up of primitive quartet j (names suffixed _j: pair data, Boys
+    F_m scaled by the prefactor, VRR geometry); `wexpr` scales its prefactor
+    (0 for a padding quartet).  Expects i1_j..i4_j, pab, pcd, Nt, x1, x3."""
+    sfx = f"_{j}"
+    w(f"{ind}const FxPrimPair bra{sfx} = pab[i1{sfx} * Nt + i2{sfx}];")
+    w(f"{ind}const double p{sfx} = bra{sfx}.p, op{sfx} = bra{sfx}.op, Px{sfx} = bra{sfx}.Px, Py{sfx} = bra{sfx}.Py, "
+      f"Pz{sfx} = bra{sfx}.Pz;")
+    w(f"{ind}const FxPrimPair ket{sfx} = pcd[i3{sfx} * Nt + i4{sfx}];")
+    w(f"{ind}const double q{sfx} = ket{sfx}.p, oq{sfx} = ket{sfx}.op, Qx{sfx} = ket{sfx}.Px, Qy{sfx} = ket{sfx}.Py, "
+      f"Qz{sfx} = ket{sfx}.Pz;")
+    w(f"{ind}const double ppq{sfx} = p{sfx} + q{sfx}, oppq{sfx} = 1.0 / ppq{sfx}, rho{sfx} = p{sfx} * q{sfx} * oppq{sfx};")
+    w(f"{ind}const double PQx{sfx} = Px{sfx} - Qx{sfx}, PQy{sfx} = Py{sfx} - Qy{sfx}, PQz{sfx} = Pz{sfx} - Qz{sfx};")
+    w(f"{ind}const double T{sfx} = rho{sfx} * (PQx{sfx} * PQx{sfx} + PQy{sfx} * PQy{sfx} + PQz{sfx} * PQz{sfx});")
+    scale = f" * {wexpr}" if wexpr else ""
+    w(f"{ind}const double pref{sfx} = FX_TWO_PI_POW_2_5 * op{sfx} * oq{sfx} * sqrt(oppq{sfx}) * bra{sfx}.K * "
+      f"ket{sfx}.K{scale};")
+    w(f"{ind}double F{sfx}[{Lsum + 1}];")
+    w(f"{ind}fx_boys<{Lsum}>(T{sfx}, boys_tab, F{sfx});")
+    for m in range(Lsum + 1):
+        w(f"{ind}const {real} s{m}{sfx} = ({real})(pref{sfx} * F{sfx}[{m}]);")
+    if Lsum == 0:
+        return
+    w(f"{ind}const double Wx{sfx} = (p{sfx} * Px{sfx} + q{sfx} * Qx{sfx}) * oppq{sfx}, "
+      f"Wy{sfx} = (p{sfx} * Py{sfx} + q{sfx} * Qy{sfx}) * oppq{sfx}, Wz{sfx} = (p{sfx} * Pz{sfx} + q{sfx} * Qz{sfx}) * oppq{sfx};")
+    for c in "xyz":
+        w(f"{ind}const {real} PA{c}{sfx} = ({real})(P{c}{sfx} - x1.{c}), WP{c}{sfx} = ({real})(W{c}{sfx} - P{c}{sfx});")
+        w(f"{ind}const {real} QC{c}{sfx} = ({real})(Q{c}{sfx} - x3.{c}), WQ{c}{sfx} = ({real})(W{c}{sfx} - Q{c}{sfx});")
+    w(f"{ind}const {real} oo2p{sfx} = ({real})(0.5 * op{sfx}), oo2q{sfx} = ({real})(0.5 * oq{sfx}), "
+      f"oo2pq{sfx} = ({real})(0.5 * oppq{sfx});")
+    w(f"{ind}const {real} oo2p_rp{sfx} = ({real})(0.5 * op{sfx} * rho{sfx} * op{sfx}), "
+      f"oo2q_rq{sfx} = ({real})(0.5 * oq{sfx} * rho{sfx} * oq{sfx});")
+    for nm in ("PAx", "PAy", "PAz", "WPx", "WPy", "WPz", "QCx", "QCy", "QCz", "WQx", "WQy", "WQz", "oo2p", "oo2q",
+               "oo2pq", "oo2p_rp", "oo2q_rq"):
+        w(f"{ind}(void){nm}{sfx};")
+
+
+_VRR_TOKEN = re.compile(r"\b(v\d+|s\d+|PA[xyz]|WP[xyz]|QC[xyz]|WQ[xyz]|oo2p|oo2q|oo2pq|oo2p_rp|oo2q_rq)\b")
+
+
+def _emit_vrr(w, vem, tpos0, nj, ind, put_fmt):
+    """The VRR of nj primitive quartets, interleaved node by node; each
+    target is handed to put_fmt(k, "v_0 + v_1 ...") as soon as all nj
+    copies of it are formed."""
+    tpos = dict(tpos0)
+
+    def put(nm):
+        k = tpos.pop(nm)
+        w(ind + put_fmt(k, " + ".join(f"{nm}_{j}" for j in range(nj))))
+    for line in vem.lines:
+        for j in range(nj):
+            w(ind + _VRR_TOKEN.sub(lambda m: m.group(1) + f"_{j}", line))
+        nm = line.split(" = ", 1)[0].split()[-1]
+        if nm in tpos:
+            put(nm)
+    for nm in list(tpos):          # targets that are base values s_m
+        put(nm)
+
+
 def _emit_fold(w, real, o, comps, icomp, fcols, idx):
     """Steps 2+3 of the folded staged routine: per ket column f, the bra HRR
     of X[., f] into registers, then every (x3 x4) component whose closed-form
@@ -519,58 +578,11 @@ def gen_class_staged(la, lb, lc, ld, real, paired=False, fold=False):
     tpos0 = {nm: k for k, nm in enumerate(tnames)}
 
     def setup(j, ind, wexpr=None):
-        """Set-up of primitive quartet j (names suffixed _j); `wexpr`
-        scales its prefactor (0 for a padding quartet)."""
-        sfx = f"_{j}"
-        w(f"{ind}const FxPrimPair bra{sfx} = pab[i1{sfx} * Nt + i2{sfx}];")
-        w(f"{ind}const double p{sfx} = bra{sfx}.p, op{sfx} = bra{sfx}.op, Px{sfx} = bra{sfx}.Px, Py{sfx} = bra{sfx}.Py, "
-          f"Pz{sfx} = bra{sfx}.Pz;")
-        w(f"{ind}const FxPrimPair ket{sfx} = pcd[i3{sfx} * Nt + i4{sfx}];")
-        w(f"{ind}const double q{sfx} = ket{sfx}.p, oq{sfx} = ket{sfx}.op, Qx{sfx} = ket{sfx}.Px, Qy{sfx} = ket{sfx}.Py, "
-          f"Qz{sfx} = ket{sfx}.Pz;")
-        w(f"{ind}const double ppq{sfx} = p{sfx} + q{sfx}, oppq{sfx} = 1.0 / ppq{sfx}, rho{sfx} = p{sfx} * q{sfx} * oppq{sfx};")
-        w(f"{ind}const double PQx{sfx} = Px{sfx} - Qx{sfx}, PQy{sfx} = Py{sfx} - Qy{sfx}, PQz{sfx} = Pz{sfx} - Qz{sfx};")
-        w(f"{ind}const double T{sfx} = rho{sfx} * (PQx{sfx} * PQx{sfx} + PQy{sfx} * PQy{sfx} + PQz{sfx} * PQz{sfx});")
-        scale = f" * {wexpr}" if wexpr else ""
-        w(f"{ind}const double pref{sfx} = FX_TWO_PI_POW_2_5 * op{sfx} * oq{sfx} * sqrt(oppq{sfx}) * bra{sfx}.K * "
-          f"ket{sfx}.K{scale};")
-        w(f"{ind}double F{sfx}[{Lsum + 1}];")
-        w(f"{ind}fx_boys<{Lsum}>(T{sfx}, boys_tab, F{sfx});")
-        for m in range(Lsum + 1):
-            w(f"{ind}const {real} s{m}{sfx} = ({real})(pref{sfx} * F{sfx}[{m}]);")
-        w(f"{ind}const double Wx{sfx} = (p{sfx} * Px{sfx} + q{sfx} * Qx{sfx}) * oppq{sfx}, "
-          f"Wy{sfx} = (p{sfx} * Py{sfx} + q{sfx} * Qy{sfx}) * oppq{sfx}, Wz{sfx} = (p{sfx} * Pz{sfx} + q{sfx} * Qz{sfx}) * oppq{sfx};")
-        for c in "xyz":
-            w(f"{ind}const {real} PA{c}{sfx} = ({real})(P{c}{sfx} - x1.{c}), WP{c}{sfx} = ({real})(W{c}{sfx} - P{c}{sfx});")
-            w(f"{ind}const {real} QC{c}{sfx} = ({real})(Q{c}{sfx} - x3.{c}), WQ{c}{sfx} = ({real})(W{c}{sfx} - Q{c}{sfx});")
-        w(f"{ind}const {real} oo2p{sfx} = ({real})(0.5 * op{sfx}), oo2q{sfx} = ({real})(0.5 * oq{sfx}), "
-          f"oo2pq{sfx} = ({real})(0.5 * oppq{sfx});")
-        w(f"{ind}const {real} oo2p_rp{sfx} = ({real})(0.5 * op{sfx} * rho{sfx} * op{sfx}), "
-          f"oo2q_rq{sfx} = ({real})(0.5 * oq{sfx} * rho{sfx} * oq{sfx});")
-        for nm in ("PAx", "PAy", "PAz", "WPx", "WPy", "WPz", "QCx", "QCy", "QCz", "WQx", "WQy", "WQz", "oo2p", "oo2q",
-                   "oo2pq", "oo2p_rp", "oo2q_rq"):
-            w(f"{ind}(void){nm}{sfx};")
-
-    tok = re.compile(r"\b(v\d+|s\d+|PA[xyz]|WP[xyz]|QC[xyz]|WQ[xyz]|oo2p|oo2q|oo2pq|oo2p_rp|oo2q_rq)\b")
+        _emit_prim_setup(w, real, Lsum, j, ind, wexpr)
 
     def vrr_lines(nj, ind):
-        """The VRR of nj primitive quartets, interleaved node by node; each
-        target goes into X (store, or add when ACC) as soon as all nj
-        copies of it are formed."""
-        tpos = dict(tpos0)
-
-        def put(nm):
-            k = tpos.pop(nm)
-            sm = " + ".join(f"{nm}_{j}" for j in range(nj))
-            w(f"{ind}if constexpr (ACC) X[{k}] += {sm}; else X[{k}] = {sm};")
-        for line in vem.lines:
-            for j in range(nj):
-                w(ind + tok.sub(lambda m: m.group(1) + f"_{j}", line))
-            nm = line.split(" = ", 1)[0].split()[-1]
-            if nm in tpos:
-                put(nm)
-        for nm in list(tpos):          # targets that are base values s_m
-            put(nm)
+        _emit_vrr(w, vem, tpos0, nj, ind,
+                  lambda k, sm: f"if constexpr (ACC) X[{k}] += {sm}; else X[{k}] = {sm};")
 
     if paired:
         # two primitive quartets per pass (the second of an odd count is a
