@@ -101,11 +101,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", default="cluster",
-                    choices=["cluster", "batched", "slab-mlp", "copy-probe", "scaling"],
+                    choices=["cluster", "batched", "slab-mlp", "copy-probe", "scaling", "multi"],
                     help="cluster: the headline 1000-atom s+p+d build; batched: 64 clusters in one batched "
                          "call vs 64 sequential builds; slab-mlp: 4000-atom s+p slab, learned vs bound-only "
                          "scheduling; copy-probe: one elementwise copy of 1 GiB, to scale HBM byte counters; "
-                         "scaling: K-build time of s+p+d clusters of 125..2000 atoms (onset of linear scaling)")
+                         "scaling: K-build time of s+p+d clusters of 125..2000 atoms (onset of linear scaling); "
+                         "multi: two densities of the 1000-atom cluster in one call vs two single builds")
     ap.add_argument("--no-tuning", action="store_true", help="ignore the autotuned kernel table")
     ap.add_argument("--no-symmetry", action="store_true", help="build every K block (no use of K = K^T)")
     args = ap.parse_args()
@@ -131,6 +132,8 @@ def main():
         return bench_slab_mlp(args, log)
     if args.workload == "scaling":
         return bench_scaling(args, log)
+    if args.workload == "multi":
+        return bench_multi(args, log)
 
     log(f"bench: generating {args.natom}-atom s+p+d cluster")
     system = synthetic.cluster(args.natom)
@@ -282,6 +285,52 @@ def bench_scaling(args, log):
                       "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
                       "config": {"workload": "s+p+d clusters of 125, 250, 500, 1000, 2000 atoms at 0.1 atoms/A^3"},
                       "series": rows}))
+
+
+def bench_multi(args, log):
+    """Two densities of the 1000-atom s+p+d cluster (the benchmark's P and a
+    second one from the same recipe, seed 7002), mixed precision: one
+    fx_exchange_multi call against two fx_exchange_ex calls."""
+    import numpy as np
+    import torch
+    import synthetic
+    import paper_1401_6961_amd as fx
+    s = synthetic.cluster(args.natom)
+    P2 = synthetic.make_density(np.random.default_rng(7002), s.atoms, s.func_atom(), 2.0)
+    tree = fx.build_quadtree_from(s)
+    Ps = [torch.from_numpy(s.P).cuda(), torch.from_numpy(P2).cuda()]
+    del P2
+    opts = fx.make_opts(precision=fx.FX_PREC_MIXED)
+    Ks = [torch.zeros_like(P) for P in Ps]
+    for _ in range(args.warmup):
+        fx.fx_exchange_multi(tree, Ps, Ks, s.tau, opts)
+    torch.cuda.synchronize()
+    log("bench: two densities in one call")
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        _, st = fx.fx_exchange_multi(tree, Ps, Ks, s.tau, opts)
+    torch.cuda.synchronize()
+    tm = (time.perf_counter() - t) / args.steps
+    log("bench: two single builds")
+    K1 = [torch.zeros_like(P) for P in Ps]
+    t = time.perf_counter()
+    q = 0
+    for P, K in zip(Ps, K1):
+        _, s1 = fx.fx_exchange_ex(tree, P, s.tau, K, opts)
+        q += s1["quartets_covered"]
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t
+    dk = max(float((a - b).abs().max()) for a, b in zip(Ks, K1))
+    print(json.dumps({"metric": "K-build s, two densities, 1000-atom s+p+d, tau=1e-8, mixed",
+                      "value": 2 * st["quartets_covered"] / tm, "unit": "quartet-density contractions/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * tm,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+                      "data": "synthetic",
+                      "config": {"workload": f"{args.natom}-atom s+p+d cluster, two densities, one call",
+                                 "nbf": s.nbf},
+                      "multi_s": tm, "two_single_s": ts, "speedup": ts / tm,
+                      "quartets": st["quartets_covered"], "single_quartets": q,
+                      "max_abs_diff_vs_single": dk}))
 
 
 def bench_batched(args, log):

@@ -175,6 +175,19 @@ fx_status fx_exchange_batched(const fx_tree* const* trees, const double* const* 
                               int32_t count, double tau, const fx_exchange_opts* opts,
                               fx_stats* stats, void* stream);
 
+/* Several densities of one system contracted with the same integrals
+ * (Eq. 6 for each): K[j] <- K_x(P[j]), j < ndens, ndens in 1..2 (else
+ * FX_ERR_UNSUPPORTED).  P, K: host arrays of ndens device pointers to n x n
+ * row-major FP64 arrays in caller order; no P may alias a K and the K must be
+ * distinct.  The metric query of Eq. (8) uses, for each density block, the
+ * largest norm over the densities, so every K[j] contains at least the
+ * quartets its own density would select (K[j] equals fx_exchange_ex(P[j])
+ * when all densities are equal).  The symmetric path (fx_symmetry) is taken
+ * when every density is bitwise symmetric.  Options and stats as in
+ * fx_exchange_ex (quartet counts are per quartet, not per density). */
+fx_status fx_exchange_multi(const fx_tree* tree, const double* const* P, double* const* K, int32_t ndens,
+                            double tau, const fx_exchange_opts* opts, fx_stats* stats, void* stream);
+
 /* Number of basis functions. */
 int32_t fx_nbf(const fx_tree* tree);
 /* Number of shells. */

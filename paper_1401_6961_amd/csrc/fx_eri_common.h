@@ -9,6 +9,10 @@
 
 #define FX_TWO_PI_POW_2_5 34.98683665524972497   // 2 pi^{5/2}
 
+// loop over the densities contracted with every quartet (NDENS, a template
+// parameter of the quartet routines and kernels)
+#define FX_FOR_DENS _Pragma("unroll") for (int _d = 0; _d < NDENS; ++_d)
+
 // compile-time flag of the staged routines: store (false) or add (true)
 template <bool B>
 struct FxAcc {
@@ -142,11 +146,12 @@ __device__ __forceinline__ double fx_comp_factor(int l, int k) {
 // of the unit, whatever order units are scheduled in.  The block is written
 // once to this class's (lb, lc, precision) slot: no atomics.
 // ---------------------------------------------------------------------------
-template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, typename Fn>
+template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, int NDENS, typename Fn>
 __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, long slot_unit, int wave,
                                               int2 (*queue)[128]) {
+    static_assert(!COOP || NDENS == 1, "the one-quartet-per-wave form contracts one density");
     constexpr int NA = fx_ncart(LA), ND = fx_ncart(LD);
-    constexpr int NK = COOP ? 1 : NA * ND;   // K elements held per lane
+    constexpr int NK = COOP ? 1 : NA * ND;   // K elements held per lane and density
     const int lane = fx_lane();
     const int u = __builtin_amdgcn_readfirstlane(A.order ? A.order[slot_unit] : (int)slot_unit);
     const int sid = A.unit_sys ? __builtin_amdgcn_readfirstlane(A.unit_sys[u]) : -1;
@@ -162,9 +167,9 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, long 
     const double* __restrict__ Qd = Bs.Qn + (long)d * S;
     const double tau = A.tau, thr = A.thr;
     const int mode = A.mode;
-    double kacc[NK];
+    double kacc[NDENS * NK];
 #pragma unroll
-    for (int i = 0; i < NK; ++i) kacc[i] = 0.0;
+    for (int i = 0; i < NDENS * NK; ++i) kacc[i] = 0.0;
 
     const long e0 = Sy.bc_off[item], e1 = Sy.bc_off[item + 1];
     int qn = 0;
@@ -172,8 +177,11 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, long 
     auto evaluate = [&](int2 q) {
         const FxShellRef rb = fx_shell(Bs, q.x), rc = fx_shell(Bs, q.y);
         if (!COOP || lane == 0) npq += (long)(ra.nprim * rb.nprim) * (rc.nprim * rd.nprim);
-        const double* Pblk = Sy.P + (long)Bs.f0[q.x] * Sy.n + Bs.f0[q.y];
-        fn(ra, rb, rc, rd, Bs, A.boys, Pblk, Sy.n, kacc, wave);
+        const long pofs = (long)Bs.f0[q.x] * Sy.n + Bs.f0[q.y];
+        const double* Pq[NDENS];
+#pragma unroll
+        for (int i = 0; i < NDENS; ++i) Pq[i] = Sy.P[i] + pofs;
+        fn(ra, rb, rc, rd, Bs, A.boys, Pq, Sy.n, kacc, wave);
     };
     auto test = [&](int b, int c) {
         const double beta = (Qa[b] * Qd[c]) * Sy.Pn[(long)b * S + c];
@@ -258,22 +266,29 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, long 
     }
     // deterministic reduction of the 64 lane partials, then one write per element
     const long rowbase = (long)Bs.f0[a] * Sy.n + Bs.f0[d];
-    double outv = 0.0;
+    double outv[NDENS];
+#pragma unroll
+    for (int j = 0; j < NDENS; ++j) outv[j] = 0.0;
     if (COOP) {
         // lane t already owns element t of the block
-        outv = kacc[0] * (fx_comp_factor(LA, lane / ND) * fx_comp_factor(LD, lane % ND));
+        outv[0] = kacc[0] * (fx_comp_factor(LA, lane / ND) * fx_comp_factor(LD, lane % ND));
     } else {
 #pragma unroll
-        for (int i = 0; i < NK; ++i) {
-            const double s = fx_wave_sum(kacc[i]);
-            if (lane == i) outv = s * (fx_comp_factor(LA, i / ND) * fx_comp_factor(LD, i % ND));
-        }
+        for (int j = 0; j < NDENS; ++j)
+#pragma unroll
+            for (int i = 0; i < NK; ++i) {
+                const double s = fx_wave_sum(kacc[j * NK + i]);
+                if (lane == i) outv[j] = s * (fx_comp_factor(LA, i / ND) * fx_comp_factor(LD, i % ND));
+            }
     }
-    double* kslot = Sy.slots + (long)A.slot_index * Sy.n * Sy.n;
-    if (lane < NA * ND) kslot[rowbase + (long)(lane / ND) * Sy.n + (lane % ND)] = outv;
-    // symmetric density: K_da = K_ad^T, and unit (d, a) does not exist
-    if (Sy.sym && a != d && lane < NA * ND)
-        kslot[(long)(Bs.f0[d] + lane % ND) * Sy.n + Bs.f0[a] + lane / ND] = outv;
+#pragma unroll
+    for (int j = 0; j < NDENS; ++j) {
+        double* kslot = Sy.slots + j * Sy.slot_stride + (long)A.slot_index * Sy.n * Sy.n;
+        if (lane < NA * ND) kslot[rowbase + (long)(lane / ND) * Sy.n + (lane % ND)] = outv[j];
+        // symmetric densities: K_da = K_ad^T, and unit (d, a) does not exist
+        if (Sy.sym && a != d && lane < NA * ND)
+            kslot[(long)(Bs.f0[d] + lane % ND) * Sy.n + Bs.f0[a] + lane / ND] = outv[j];
+    }
     if (A.times && lane == 0) A.times[u] = (float)(wall_clock64() - t_start);
     if (A.counters) {
         long np = npq;
@@ -291,7 +306,7 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, long 
 // of workgroups (fx_xcd_remap) so that neighbouring units -- which share
 // density and pair data -- run on one XCD and its L2.  K does not depend on
 // the mapping.
-template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, typename Fn>
+template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, int NDENS, typename Fn>
 __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
     __shared__ int2 queue[WAVES][128];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -299,7 +314,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
     if (A.flags & FX_LAUNCH_XCD) blk = fx_xcd_remap(blk, gridDim.x);
     const long slot_unit = blk * WAVES + wave;
     if (slot_unit >= A.nunits) return;
-    fx_class_unit<LA, LB, LC, LD, COOP, WAVES>(A, fn, slot_unit, wave, queue);
+    fx_class_unit<LA, LB, LC, LD, COOP, WAVES, NDENS>(A, fn, slot_unit, wave, queue);
 }
 
 // Thread variant: one quartet per lane.
@@ -312,13 +327,15 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
 #ifndef FX_THREAD_MIN_WAVES_f32
 #define FX_THREAD_MIN_WAVES_f32 1
 #endif
+// Instantiated for one and for two densities (FxClassArgs::ndens).
 #define FX_THREAD_KERNEL(la, lb, lc, ld, cls, prec)                                                     \
+    template <int NDENS>                                                                                 \
     __global__ __launch_bounds__(64 * FX_CLASS_WAVES, FX_THREAD_MIN_WAVES_##prec) void                  \
         fx_k_##cls##_##prec(FxClassArgs A) {                                                            \
-        fx_class_body<la, lb, lc, ld, false, FX_CLASS_WAVES>(                                           \
+        fx_class_body<la, lb, lc, ld, false, FX_CLASS_WAVES, NDENS>(                                    \
             A, [](const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc, const FxShellRef& rd, \
-                  const FxDevBasis& B, const double* bt, const double* P, long n, double* k, int) {       \
-                eri_##cls##_##prec(ra, rb, rc, rd, B, bt, P, n, k);                                      \
+                  const FxDevBasis& B, const double* bt, const double* const* P, long n, double* k, int) { \
+                eri_##cls##_##prec<NDENS>(ra, rb, rc, rd, B, bt, P, n, k);                               \
             });                                                                                          \
     }
 
@@ -326,18 +343,22 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
 #define FX_COOP_KERNEL(la, lb, lc, ld, cls, prec, real)                                                 \
     __global__ __launch_bounds__(64 * FX_COOP_WAVES) void fx_kc_##cls##_##prec(FxClassArgs A) {        \
         __shared__ real lds[FX_COOP_WAVES * coop_##cls##_##prec::NSLOT];                                 \
-        fx_class_body<la, lb, lc, ld, true, FX_COOP_WAVES>(                                             \
+        fx_class_body<la, lb, lc, ld, true, FX_COOP_WAVES, 1>(                                          \
             A, [&](const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc, const FxShellRef& rd, \
-                   const FxDevBasis& B, const double* bt, const double* P, long n, double* k, int w) {    \
-                eri_##cls##_##prec##_coop(ra, rb, rc, rd, B, bt, P, n,                                   \
+                   const FxDevBasis& B, const double* bt, const double* const* P, long n, double* k, int w) { \
+                eri_##cls##_##prec##_coop(ra, rb, rc, rd, B, bt, P[0], n,                                \
                                           lds + w * coop_##cls##_##prec::NSLOT, k[0]);                   \
             });                                                                                          \
     }
 
 #define FX_LAUNCH_THREAD(cls, prec)                                                                     \
-    hipLaunchKernelGGL(fx_k_##cls##_##prec,                                                             \
-                       dim3((A.nunits + FX_CLASS_WAVES - 1) / FX_CLASS_WAVES),         \
-                       dim3(64 * FX_CLASS_WAVES), 0, st, A)
+    do {                                                                                                 \
+        const dim3 g((A.nunits + FX_CLASS_WAVES - 1) / FX_CLASS_WAVES), b(64 * FX_CLASS_WAVES);          \
+        if (A.ndens == 2)                                                                                \
+            hipLaunchKernelGGL(fx_k_##cls##_##prec<2>, g, b, 0, st, A);                                  \
+        else                                                                                             \
+            hipLaunchKernelGGL(fx_k_##cls##_##prec<1>, g, b, 0, st, A);                                  \
+    } while (0)
 #define FX_LAUNCH_COOP(cls, prec)                                                                       \
     hipLaunchKernelGGL(fx_kc_##cls##_##prec,                                                            \
                        dim3((A.nunits + FX_COOP_WAVES - 1) / FX_COOP_WAVES),           \
@@ -350,7 +371,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
     FX_COOP_KERNEL(la, lb, lc, ld, cls, f64, double)                                                    \
     FX_COOP_KERNEL(la, lb, lc, ld, cls, f32, float)                                                     \
     int fx_launch_##cls(int prec32, int variant, FxClassArgs A, hipStream_t st) {              \
-        if (variant == 1) {                                                                              \
+        if (variant == 1 && A.ndens == 1) {                                                              \
             if (prec32) FX_LAUNCH_COOP(cls, f32); else FX_LAUNCH_COOP(cls, f64);                         \
             return 1;                                                                                    \
         }                                                                                                \

@@ -532,8 +532,8 @@ struct Frontier {
 // one system of a call: tree, density, output and its per-call arrays
 struct SysCtx {
     const fx_tree* T = nullptr;
-    const double* P = nullptr;
-    double* K = nullptr;
+    const double* P[FX_MAX_DENS] = {nullptr, nullptr};
+    double* K[FX_MAX_DENS] = {nullptr, nullptr};
     double* Pn = nullptr;
     std::vector<double*> Psq;
     double* slots = nullptr;
@@ -560,6 +560,7 @@ struct ExCtx {
     long cap;
     int L;                          // slot layout: (highest l + 1)^2 (x2 in mixed mode)
     int nslot;
+    int ndens = 1;                  // densities per system, contracted with the same integrals
     bool collect = false;           // batched: keep leaf segments for one launch per class
     bool use_graph = false;
     std::vector<std::unique_ptr<LeafSeg>> segs;
@@ -621,13 +622,14 @@ static std::unique_ptr<LeafSeg> prepare_seg(ExCtx& c, SysCtx& sc, const Frontier
     A.release(upos);
     FxSys& Y = seg->sys;
     Y.basis = T->basis;
-    Y.P = sc.P;
+    for (int j = 0; j < FX_MAX_DENS; ++j) Y.P[j] = sc.P[j < c.ndens ? j : 0];
     Y.n = T->n;
     Y.Pn = sc.Pn;
     Y.bc_off = f.bc_off;
     Y.bc = f.bc;
     Y.cls_off = nullptr;
     Y.slots = sc.slots;
+    Y.slot_stride = (long)c.nslot * T->n * T->n;
     Y.sym = sc.sym;
     const long ne = std::max(1L, f.e_count);
     if (T->single_shell_leaves) {
@@ -735,6 +737,7 @@ static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
     std::vector<float> hfeat, htime;
     FxClassArgs args{};
     args.boys = segs[0]->T->boys;
+    args.ndens = c.ndens;
     args.tau = c.tau;
     args.thr = c.thr;
     const float* mean_np = segs[0]->T->mean_np;
@@ -958,10 +961,20 @@ static fx_exchange_opts checked_opts(const fx_exchange_opts* opts) {
 // Exchange of one or several systems.  Several systems are traversed one
 // after another, their leaf segments kept, and every class kernel is then
 // launched once over the units of all systems.
+// Ps, Ks: count * ndens device pointers, system-major.
 static void exchange_many(const fx_tree* const* trees, const double* const* Ps, double* const* Ks, int count,
-                          double tau, const fx_exchange_opts* opts, fx_stats* stats, hipStream_t st) {
+                          int ndens, double tau, const fx_exchange_opts* opts, fx_stats* stats, hipStream_t st) {
     auto t0 = std::chrono::steady_clock::now();
-    for (int i = 0; i < count; ++i) validate_exchange(trees[i], Ps[i], tau, Ks[i]);
+    if (ndens < 1 || ndens > FX_MAX_DENS)
+        fx_fail(FX_ERR_UNSUPPORTED, "ndens must be 1.." + std::to_string(FX_MAX_DENS));
+    for (int i = 0; i < count; ++i)
+        for (int j = 0; j < ndens; ++j) {
+            validate_exchange(trees[i], Ps[i * ndens + j], tau, Ks[i * ndens + j]);
+            for (int k = 0; k < ndens; ++k) {
+                if (Ps[i * ndens + j] == Ks[i * ndens + k]) fx_fail(FX_ERR_INVALID_ARG, "a density aliases a K");
+                if (k != j && Ks[i * ndens + j] == Ks[i * ndens + k]) fx_fail(FX_ERR_INVALID_ARG, "two K alias");
+            }
+        }
     const fx_exchange_opts o = checked_opts(opts);
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (count == 0) return;
@@ -976,6 +989,7 @@ static void exchange_many(const fx_tree* const* trees, const double* const* Ps, 
     c.cap = o.max_frontier_entries > 0 ? o.max_frontier_entries : (1L << 30);
     c.stats = stats;
     c.profile = o.profile;
+    c.ndens = ndens;
     c.collect = count > 1;
     c.use_graph = o.use_graph != 0;
     c.rec = g_recording;
@@ -1000,14 +1014,25 @@ static void exchange_many(const fx_tree* const* trees, const double* const* Ps, 
         SysCtx& sc = sys[i];
         const fx_tree* T = trees[i];
         sc.T = T;
-        sc.P = Ps[i];
-        sc.K = Ks[i];
+        for (int j = 0; j < ndens; ++j) {
+            sc.P[j] = Ps[i * ndens + j];
+            sc.K[j] = Ks[i * ndens + j];
+        }
         const int S = T->S;
         const long n = T->n, nn = n * n;
         if (stats) stats->levels = std::max(stats->levels, (int)T->levels.size());
-        // density norms
+        // density norms; with several densities the largest, so that the
+        // screening bounds every density's contribution
         sc.Pn = A.get<double>((size_t)S * S);
-        fx_launch_pnorm(sc.P, n, T->basis.l, T->basis.f0, S, sc.Pn, st);
+        fx_launch_pnorm(sc.P[0], n, T->basis.l, T->basis.f0, S, sc.Pn, st);
+        if (ndens > 1) {
+            double* Pn2 = A.get<double>((size_t)S * S);
+            for (int j = 1; j < ndens; ++j) {
+                fx_launch_pnorm(sc.P[j], n, T->basis.l, T->basis.f0, S, Pn2, st);
+                fx_launch_max_inplace(sc.Pn, Pn2, (long)S * S, st);
+            }
+            A.release(Pn2);
+        }
         const int nl = (int)T->levels.size();
         sc.Psq.resize(nl);
         for (int k = nl - 1; k >= 0; --k) {
@@ -1025,13 +1050,13 @@ static void exchange_many(const fx_tree* const* trees, const double* const* Ps, 
         if (o.symmetry == FX_SYM_AUTO && (n + 31) / 32 <= 65535) {
             int* flag = A.get<int>(1);
             fx_launch_fill_i32(flag, 1, 0, st);
-            fx_launch_psym(sc.P, n, flag, st);
+            for (int j = 0; j < ndens; ++j) fx_launch_psym(sc.P[j], n, flag, st);
             sc.sym = read1(flag, st) == 0 ? 1 : 0;
             A.release(flag);
         }
         if (stats) stats->symmetric_systems += sc.sym;
-        sc.slots = A.get<double>((size_t)c.nslot * nn);
-        fx_launch_fill(sc.slots, (long)c.nslot * nn, 0.0, st);
+        sc.slots = A.get<double>((size_t)c.nslot * nn * ndens);
+        fx_launch_fill(sc.slots, (long)c.nslot * nn * ndens, 0.0, st);
         FX_HIP(hipGetLastError());
         // root task
         const double q0 = read1(T->d_Qsq[0], st), p0 = read1(sc.Psq[0], st);
@@ -1059,7 +1084,8 @@ static void exchange_many(const fx_tree* const* trees, const double* const* Ps, 
     }
     for (int i = 0; i < count; ++i) {
         const long nn = (long)sys[i].T->n * sys[i].T->n;
-        fx_launch_finalize(sys[i].slots, c.nslot, nn, o.alpha, o.beta, sys[i].K, st);
+        for (int j = 0; j < ndens; ++j)
+            fx_launch_finalize(sys[i].slots + (long)j * c.nslot * nn, c.nslot, nn, o.alpha, o.beta, sys[i].K[j], st);
     }
     FX_HIP(hipGetLastError());
     struct EvGuard {
@@ -1103,7 +1129,7 @@ static void exchange_many(const fx_tree* const* trees, const double* const* Ps, 
 
 static void exchange_impl(const fx_tree* T, const double* P, double tau, double* K, const fx_exchange_opts* opts,
                           fx_stats* stats, hipStream_t st) {
-    exchange_many(&T, &P, &K, 1, tau, opts, stats, st);
+    exchange_many(&T, &P, &K, 1, 1, tau, opts, stats, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1139,7 +1165,15 @@ fx_status fx_exchange_batched(const fx_tree* const* trees, const double* const* 
                               double tau, const fx_exchange_opts* opts, fx_stats* stats, void* stream) {
     return fx_guard([&] {
         if (count < 0 || (count > 0 && (!trees || !P || !K))) fx_fail(FX_ERR_INVALID_ARG, "bad batch arrays");
-        exchange_many(trees, P, K, count, tau, opts, stats, (hipStream_t)stream);
+        exchange_many(trees, P, K, count, 1, tau, opts, stats, (hipStream_t)stream);
+    });
+}
+
+fx_status fx_exchange_multi(const fx_tree* tree, const double* const* P, double* const* K, int32_t ndens, double tau,
+                            const fx_exchange_opts* opts, fx_stats* stats, void* stream) {
+    return fx_guard([&] {
+        if (!P || !K) fx_fail(FX_ERR_INVALID_ARG, "P and K must be arrays of ndens device pointers");
+        exchange_many(&tree, P, K, 1, ndens, tau, opts, stats, (hipStream_t)stream);
     });
 }
 

@@ -5,6 +5,7 @@
 
 #define FX_CLASS_WAVES 4          // waves (work units) per thread-variant workgroup
 #define FX_COOP_WAVES 2           // waves per cooperative-variant workgroup
+#define FX_MAX_DENS 2             // densities contracted with the same integrals
 
 // Boys table: row i holds F_j(T_i), j = 0..14 (highest m 8 + 6 Taylor terms),
 // then e^{-T_i} in column 15; T_i = i / 32, i = 0..FX_BOYS_NROW-1.
@@ -44,13 +45,14 @@ struct FxDevBasis {
 // One system (or traversal chunk) as seen by the class kernels.
 struct FxSys {
     FxDevBasis basis;
-    const double* P;
+    const double* P[FX_MAX_DENS];     // densities (n x n, caller order); the first FxClassArgs::ndens are used
     long n;
-    const double* Pn;                 // [S*S] shell-level ||P_bc||_F
+    const double* Pn;                 // [S*S] shell-level ||P_bc||_F (largest over the densities)
     const long* bc_off;               // per leaf item: offsets into bc
     const int2* bc;                   // (B, C) leaf nodes
     const long* cls_off;              // single-shell leaves: per item 10 class offsets, else null
-    double* slots;                    // K slots of this system, n*n each
+    double* slots;                    // K slots of this system, n*n each; density j's at slots + j*slot_stride
+    long slot_stride;
     int sym;                          // 1: only units a <= d (tree order) exist; each writes K_ad and K_da
 };
 
@@ -79,6 +81,7 @@ struct FxClassArgs {
     double tau, thr;
     int mode;                         // FX_MODE_*
     int flags;                        // FX_LAUNCH_*
+    int ndens;                        // densities per system (1 or 2)
     unsigned long long* counters;     // [3]: quartets, primitive quartets, quartets that also stand
                                       // for their mirror (symmetric system, a != d) (nullable)
     float* times;                     // per-unit wall-clock ticks (nullable; timing probes)

@@ -41,6 +41,7 @@ void fx_launch_unit_count(const int2* items, long nitems, const int* leaf_lofs, 
                           hipStream_t st);
 void fx_launch_unit_write(const int2* items, long nitems, long item_base, const int* leaf_lofs, const int* leaf_lsh,
                           int sym, const long* upos, int* units, hipStream_t st);
+void fx_launch_max_inplace(double* a, const double* b, long n, hipStream_t st);
 // flag <- 1 if P (n x n) is not bitwise symmetric; flag must be 0 on entry
 void fx_launch_psym(const double* P, long n, int* flag, hipStream_t st);
 void fx_launch_class_sort(const long* bc_off, const int2* bc, long nitems, const int* l, int2* out, long* cls_off,

@@ -410,6 +410,16 @@ void fx_launch_unit_write(const int2* items, long nitems, long item_base, const 
                            leaf_lsh, sym, upos, units);
 }
 
+// a[i] = max(a[i], b[i])
+__global__ void fx_k_max_inplace(double* __restrict__ a, const double* __restrict__ b, long n) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = fmax(a[i], b[i]);
+}
+
+void fx_launch_max_inplace(double* a, const double* b, long n, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(fx_k_max_inplace, dim3((n + 255) / 256), dim3(256), 0, st, a, b, n);
+}
+
 // ---------------------------------------------------------------------------
 // Bitwise symmetry test of P: 32x32 tiles (bi <= bj) and their mirror tiles
 // staged through LDS, so both reads are coalesced.  Any mismatch (NaN

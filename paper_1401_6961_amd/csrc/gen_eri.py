@@ -281,9 +281,10 @@ def gen_class(la, lb, lc, ld, real, diag=False):
         w(f"    const FxDevBasis& B, const double* __restrict__ boys_tab) {{")
         w("  const FxShellRef& ra = s0; const FxShellRef& rb = s1; const FxShellRef& rc = s0; const FxShellRef& rd = s1;")
     else:
+        w("template <int NDENS>")
         w(f"__device__ __forceinline__ void {fname}(const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc,")
         w(f"    const FxShellRef& rd, const FxDevBasis& B,")
-        w(f"    const double* __restrict__ boys_tab, const double* __restrict__ Pmat, long ldp, double* __restrict__ kacc) {{")
+        w(f"    const double* __restrict__ boys_tab, const double* const* __restrict__ Pq, long ldp, double* __restrict__ kacc) {{")
     roles = ["ra", "rb", "rc", "rd"]
     x = [roles[r] for r in o]
     w(f"  const FxShellRef& x1 = {x[0]}; const FxShellRef& x2 = {x[1]}; const FxShellRef& x3 = {x[2]}; const FxShellRef& x4 = {x[3]};")
@@ -365,14 +366,15 @@ def gen_class(la, lb, lc, ld, real, diag=False):
         for kl, lam in enumerate(comps[2]):
             fac = comp_factor(nu) * comp_factor(lam)
             pv = f"pv{jn}_{kl}"
-            if abs(fac - 1.0) < 1e-15:
-                w(f"  const double {pv} = Pmat[{jn} * ldp + {kl}];")
-            else:
-                w(f"  const double {pv} = Pmat[{jn} * ldp + {kl}] * {fac!r};")
-                cflops += 1
+            scale = "" if abs(fac - 1.0) < 1e-15 else f" * {fac!r}"
+            w(f"  double {pv}[NDENS];")
+            w(f"  FX_FOR_DENS {pv}[_d] = Pq[_d][{jn} * ldp + {kl}]{scale};")
+            cflops += 1 if scale else 0
+            nkb = len(comps[0]) * nd
             for im in range(len(comps[0])):
                 for ls_ in range(nd):
-                    w(f"  kacc[{im * nd + ls_}] += (double){ints[(im, jn, kl, ls_)]} * {pv};")
+                    w(f"  {{ const double _v = (double){ints[(im, jn, kl, ls_)]}; "
+                      f"FX_FOR_DENS kacc[_d * {nkb} + {im * nd + ls_}] += _v * {pv}[_d]; }}")
                     cflops += 2
     w("}")
     return "\n".join(out), vem.flops, hem.flops + cflops
@@ -444,14 +446,14 @@ def _emit_fold(w, real, o, comps, icomp, fcols, idx):
     fl = 0
     nd = len(comps[3])
     index = [{t: k for k, t in enumerate(comps[r])} for r in range(4)]
+    nkb = len(comps[0]) * nd
     for jn, nu in enumerate(comps[1]):
         for kl, lam in enumerate(comps[2]):
             fac = comp_factor(nu) * comp_factor(lam)
-            if abs(fac - 1.0) < 1e-15:
-                w(f"  const double pv{jn}_{kl} = Pmat[{jn} * ldp + {kl}];")
-            else:
-                w(f"  const double pv{jn}_{kl} = Pmat[{jn} * ldp + {kl}] * {fac!r};")
-                fl += 1
+            scale = "" if abs(fac - 1.0) < 1e-15 else f" * {fac!r}"
+            w(f"  double pv{jn}_{kl}[NDENS];")
+            w(f"  FX_FOR_DENS pv{jn}_{kl}[_d] = Pq[_d][{jn} * ldp + {kl}]{scale};")
+            fl += 1 if scale else 0
     w("  const double CDx2 = CDx * CDx, CDy2 = CDy * CDy, CDz2 = CDz * CDz;")
     w("  (void)CDx2; (void)CDy2; (void)CDz2;")
     powname = {1: "CD{}", 2: "CD{}2"}
@@ -502,11 +504,13 @@ def _emit_fold(w, real, o, comps, icomp, fcols, idx):
                             if coef:
                                 nu_ += 1
                                 us[key] = f"u{nu_}"
-                                w(f"    const double u{nu_} = {coef} * pv{jn}_{kl};")
+                                w(f"    double u{nu_}[NDENS];")
+                                w(f"    FX_FOR_DENS u{nu_}[_d] = {coef} * pv{jn}_{kl}[_d];")
                                 fl += 1 + len(parts) + (fac != 1)
                             else:
                                 us[key] = f"pv{jn}_{kl}"
-                        w(f"    kacc[{im * nd + ls_}] += (double){yf[(t1, t2)]} * {us[key]};")
+                        w(f"    {{ const double _v = (double){yf[(t1, t2)]}; "
+                          f"FX_FOR_DENS kacc[_d * {nkb} + {im * nd + ls_}] += _v * {us[key]}[_d]; }}")
                         fl += 2
         w("  }")
     return fl
@@ -553,9 +557,10 @@ def gen_class_staged(la, lb, lc, ld, real, paired=False, fold=False):
     prec = "f32" if real == "float" else "f64"
     w(f"// class ({LNAME[la]}{LNAME[lb]}|{LNAME[lc]}{LNAME[ld]}) {prec}, staged; internal order "
       f"({'abcd'[o[0]]}{'abcd'[o[1]]}|{'abcd'[o[2]]}{'abcd'[o[3]]}); X {NX}, Y {NY} private slots")
+    w("template <int NDENS>")
     w(f"__device__ __forceinline__ void eri_{cls}_{prec}(const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc,")
     w(f"    const FxShellRef& rd, const FxDevBasis& B,")
-    w(f"    const double* __restrict__ boys_tab, const double* __restrict__ Pmat, long ldp, double* __restrict__ kacc) {{")
+    w(f"    const double* __restrict__ boys_tab, const double* const* __restrict__ Pq, long ldp, double* __restrict__ kacc) {{")
     roles = ["ra", "rb", "rc", "rd"]
     x = [roles[r] for r in o]
     w(f"  const FxShellRef& x1 = {x[0]}; const FxShellRef& x2 = {x[1]}; const FxShellRef& x3 = {x[2]}; const FxShellRef& x4 = {x[3]};")
@@ -657,11 +662,10 @@ def gen_class_staged(la, lb, lc, ld, real, paired=False, fold=False):
             fac = comp_factor(nu) * comp_factor(lam)
             pv = f"pv{jn}_{kl}"
             pvs[(jn, kl)] = pv
-            if abs(fac - 1.0) < 1e-15:
-                w(f"  const double {pv} = Pmat[{jn} * ldp + {kl}];")
-            else:
-                w(f"  const double {pv} = Pmat[{jn} * ldp + {kl}] * {fac!r};")
-                hflops += 1
+            scale = "" if abs(fac - 1.0) < 1e-15 else f" * {fac!r}"
+            w(f"  double {pv}[NDENS];")
+            w(f"  FX_FOR_DENS {pv}[_d] = Pq[_d][{jn} * ldp + {kl}]{scale};")
+            hflops += 1 if scale else 0
     for ia, a in enumerate(icomp[0]):
         for ib, b in enumerate(icomp[1]):
             hem = Emitter(real)
@@ -692,8 +696,9 @@ def gen_class_staged(la, lb, lc, ld, real, paired=False, fold=False):
                     contr.append((im * nd + ls_, nm, pvs[(jn, kl)]))
             for line in hem.lines:
                 w("    " + line)
+            nkb = len(comps[0]) * nd
             for slot, nm, pv in contr:
-                w(f"    kacc[{slot}] += (double){nm} * {pv};")
+                w(f"    {{ const double _v = (double){nm}; FX_FOR_DENS kacc[_d * {nkb} + {slot}] += _v * {pv}[_d]; }}")
                 hflops += 2
             w("  }")
             hflops += hem.flops

@@ -77,7 +77,8 @@ class fx_stats(ctypes.Structure):
                 "class_prec_quartets": np.array(self.class_prec_quartets, dtype=np.int64).reshape(81, 2)}
 
 
-EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_batched", "fx_nbf", "fx_nshell",
+EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_batched", "fx_exchange_multi", "fx_nbf",
+            "fx_nshell",
             "fx_tree_perm", "fx_tree_levels", "fx_tree_schwarz", "fx_tree_free", "fx_set_allocator",
             "fx_status_string", "fx_last_error_message", "fx_plan_tree", "fx_hilbert_key3",
             "fx_set_class_variant", "fx_get_class_variant", "fx_class_variants_available",
@@ -102,7 +103,9 @@ def lib():
     L.fx_exchange_ex.argtypes = [vp, vp, dbl, vp, ctypes.POINTER(fx_exchange_opts), ctypes.POINTER(fx_stats), vp]
     L.fx_exchange_batched.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl,
                                       ctypes.POINTER(fx_exchange_opts), ctypes.POINTER(fx_stats), vp]
-    for f in ("fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_batched", "fx_tree_perm",
+    L.fx_exchange_multi.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl,
+                                    ctypes.POINTER(fx_exchange_opts), ctypes.POINTER(fx_stats), vp]
+    for f in ("fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_batched", "fx_exchange_multi", "fx_tree_perm",
               "fx_tree_schwarz", "fx_set_allocator", "fx_plan_tree"):
         getattr(L, f).restype = ctypes.c_int
     L.fx_nbf.argtypes = [vp]
@@ -299,6 +302,24 @@ def fx_exchange_batched(trees, Ps, Ks, tau, opts=None, stream=None):
     o = opts if opts is not None else make_opts()
     _check(lib().fx_exchange_batched(th, ph, kh, count, float(tau), ctypes.byref(o), ctypes.byref(st),
                                      _stream_ptr(stream)))
+    return Ks, st.as_dict()
+
+
+def fx_exchange_multi(tree: Tree, Ps, Ks, tau, opts=None, stream=None):
+    """Several densities of one system, contracted with the same integrals."""
+    nd = len(Ps)
+    if len(Ks) != nd:
+        raise ValueError("one K per density")
+    for P, K in zip(Ps, Ks):
+        _check_matrix(P, tree.nbf, "P")
+        _check_matrix(K, tree.nbf, "K")
+    VP = ctypes.c_void_p * nd
+    ph = VP(*[P.data_ptr() for P in Ps])
+    kh = VP(*[K.data_ptr() for K in Ks])
+    st = fx_stats()
+    o = opts if opts is not None else make_opts()
+    _check(lib().fx_exchange_multi(tree.handle, ph, kh, nd, float(tau), ctypes.byref(o), ctypes.byref(st),
+                                   _stream_ptr(stream)))
     return Ks, st.as_dict()
 
 
