@@ -181,8 +181,9 @@ fx_status fx_exchange_batched(const fx_tree* const* trees, const double* const* 
  * row-major FP64 arrays in caller order; no P may alias a K and the K must be
  * distinct.  The metric query of Eq. (8) uses, for each density block, the
  * largest norm over the densities, so every K[j] contains at least the
- * quartets its own density would select (K[j] equals fx_exchange_ex(P[j])
- * when all densities are equal).  The symmetric path (fx_symmetry) is taken
+ * quartets its own density would select (when all densities are equal,
+ * K[j] equals fx_exchange_ex(P[j]): bitwise in FP64, to rounding in mixed
+ * precision).  The symmetric path (fx_symmetry) is taken
  * when every density is bitwise symmetric.  Options and stats as in
  * fx_exchange_ex (quartet counts are per quartet, not per density). */
 fx_status fx_exchange_multi(const fx_tree* tree, const double* const* P, double* const* K, int32_t ndens,

@@ -3,7 +3,8 @@
 For every angular-momentum class and precision it chooses the kernel form
 (one quartet per lane, or one quartet per wave with LDS intermediates, where
 both are built) and the launch mapping (plain or XCD-aware workgroup order)
-that run fastest on a representative workload.  Each candidate setting is
+that run fastest on a representative workload.  Classes built by default to
+run both precisions in one pass (variant 2 on the FP64 entry) keep it.  Each candidate setting is
 applied to all classes at once, the workload is built with per-launch HIP
 event timing, and the fastest setting per (class, precision) wins.  K does
 not depend on these choices (tests check this bitwise).
@@ -51,11 +52,16 @@ def tune(natom=300, with_d=True, seed=1002, repeats=2, log=print):
     P = torch.from_numpy(system.P).cuda()
     K = torch.zeros_like(P)
     configs = [(v, f) for v in (0, 1) for f in (0, 1)]
+    # classes built by default in one pass for both precisions (variant 2 on
+    # the FP64 entry) keep that choice; the sweep covers the other entries
+    dual = {cls for cls in range(81) if fx.fx_get_class_variant(cls, 0) == 2}
     times = {}
     for v, f in configs:
         for cls in range(81):
             for p in (0, 1):
-                if fx.fx_class_variants_available(cls) & (1 << v):
+                if cls in dual:
+                    fx.fx_set_class_variant(cls, p, 2 if p == 0 else 0)
+                elif fx.fx_class_variants_available(cls) & (1 << v):
                     fx.fx_set_class_variant(cls, p, v)
                 else:
                     fx.fx_set_class_variant(cls, p, 0 if v else 1)
@@ -71,6 +77,9 @@ def tune(natom=300, with_d=True, seed=1002, repeats=2, log=print):
              "device": torch.cuda.get_device_name(0), "classes": {}}
     for cls in range(81):
         for p in (0, 1):
+            if cls in dual:
+                table["classes"][f"{cls}:{p}"] = {"variant": 2 if p == 0 else 0, "flags": 0, "ms": None}
+                continue
             cands = [(times[(v, f)][cls, p], v, f) for (v, f) in configs
                      if fx.fx_class_variants_available(cls) & (1 << v) and times[(v, f)][cls, p] > 0]
             if not cands:

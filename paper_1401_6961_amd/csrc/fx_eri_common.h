@@ -146,10 +146,15 @@ __device__ __forceinline__ double fx_comp_factor(int l, int k) {
 // of the unit, whatever order units are scheduled in.  The block is written
 // once to this class's (lb, lc, precision) slot: no atomics.
 // ---------------------------------------------------------------------------
-template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, int NDENS, typename Fn>
-__device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, long slot_unit, int wave,
-                                              int2 (*queue)[128]) {
+//
+// DUAL (mixed precision in one pass): each candidate is screened once and
+// queued for the FP64 routine `fn` (beta >= thr) or the FP32 routine `fn2`
+// (beta < thr); both accumulate into the same FP64 K block.
+template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, int NDENS, bool DUAL, typename Fn, typename Fn2>
+__device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 fn2, long slot_unit, int wave,
+                                              int2 (*queue)[128], int2 (*queue2)[128]) {
     static_assert(!COOP || NDENS == 1, "the one-quartet-per-wave form contracts one density");
+    static_assert(!COOP || !DUAL, "the one-quartet-per-wave form runs one precision");
     constexpr int NA = fx_ncart(LA), ND = fx_ncart(LD);
     constexpr int NK = COOP ? 1 : NA * ND;   // K elements held per lane and density
     const int lane = fx_lane();
@@ -172,28 +177,35 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, long 
     for (int i = 0; i < NDENS * NK; ++i) kacc[i] = 0.0;
 
     const long e0 = Sy.bc_off[item], e1 = Sy.bc_off[item + 1];
-    int qn = 0;
-    long nq = 0, npq = 0;
-    auto evaluate = [&](int2 q) {
+    int qn = 0, qn2 = 0;                  // queued candidates (FP64 or only queue; FP32 queue)
+    long nq = 0, npq = 0, nq2 = 0, npq2 = 0;
+    auto evaluate = [&](int2 q, auto& f, long& np) {
         const FxShellRef rb = fx_shell(Bs, q.x), rc = fx_shell(Bs, q.y);
-        if (!COOP || lane == 0) npq += (long)(ra.nprim * rb.nprim) * (rc.nprim * rd.nprim);
+        if (!COOP || lane == 0) np += (long)(ra.nprim * rb.nprim) * (rc.nprim * rd.nprim);
         const long pofs = (long)Bs.f0[q.x] * Sy.n + Bs.f0[q.y];
         const double* Pq[NDENS];
 #pragma unroll
         for (int i = 0; i < NDENS; ++i) Pq[i] = Sy.P[i] + pofs;
-        fn(ra, rb, rc, rd, Bs, A.boys, Pq, Sy.n, kacc, wave);
+        f(ra, rb, rc, rd, Bs, A.boys, Pq, Sy.n, kacc, wave);
     };
-    auto test = [&](int b, int c) {
+    // 0: culled; 1: first queue; 2: second queue (DUAL, beta < thr)
+    auto test = [&](int b, int c) -> int {
         const double beta = (Qa[b] * Qd[c]) * Sy.Pn[(long)b * S + c];
-        bool ok = beta > tau;
-        if (mode == FX_MODE_MIXED_HI) ok = ok && !(beta < thr);
-        else if (mode == FX_MODE_MIXED_LO) ok = ok && (beta < thr);
-        return ok;
+        if (!(beta > tau)) return 0;
+        if (DUAL) return beta < thr ? 2 : 1;
+        if (mode == FX_MODE_MIXED_HI) return beta < thr ? 0 : 1;
+        if (mode == FX_MODE_MIXED_LO) return beta < thr ? 1 : 0;
+        return 1;
     };
-    auto push = [&](bool ok, int b, int c) {
-        const uint64_t m = __ballot(ok);
-        if (ok) queue[wave][qn + fx_mbcnt(m)] = make_int2(b, c);
+    auto push = [&](int cat, int b, int c) {
+        const uint64_t m = __ballot(cat == 1);
+        if (cat == 1) queue[wave][qn + fx_mbcnt(m)] = make_int2(b, c);
         qn += __popcll(m);
+        if (DUAL) {
+            const uint64_t m2 = __ballot(cat == 2);
+            if (cat == 2) queue2[wave][qn2 + fx_mbcnt(m2)] = make_int2(b, c);
+            qn2 += __popcll(m2);
+        }
     };
     // Candidate cursor: single-shell leaves read the item's (lb, lc) segment
     // (leaf index == shell index); larger leaves enumerate b in B, c in C.
@@ -203,11 +215,11 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, long 
     int kc = 0, maxc = 0, nb = 0, nc = 0, ob = 0, oc = 0;
     while (true) {
         // fill: screen candidates until a full batch is queued or none are left
-        while (qn < 64) {
+        while (qn < 64 && qn2 < 64) {
             if (seg) {
                 if (cur >= cend) break;
                 const long e = cur + lane;
-                bool ok = false;
+                int ok = 0;
                 int b = 0, c = 0;
                 if (e < cend) {
                     const int2 bc = Sy.bc[e];
@@ -234,7 +246,7 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, long 
                     cur += 64;
                     continue;
                 }
-                bool ok = false;
+                int ok = 0;
                 int b = 0, c = 0;
                 if (kc < nb * nc) {
                     const int kb = kc / nc;
@@ -247,22 +259,28 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, long 
             }
         }
         fx_wave_sync();
-        if (qn == 0) break;
-        // evaluate one batch (the only call site of the quartet routine)
-        const int nbatch = qn < 64 ? qn : 64;
-        const int2 t = queue[wave][lane + 64];
-        if (COOP) {
-            // the whole wave evaluates the queued quartets one after another
-            for (int i = 0; i < nbatch; ++i) evaluate(queue[wave][i]);
-        } else {
-            const int2 q = queue[wave][lane];
-            if (lane < nbatch) evaluate(q);
-        }
-        nq += nbatch;
-        fx_wave_sync();
-        queue[wave][lane] = t;
-        qn -= nbatch;
-        fx_wave_sync();
+        if (qn == 0 && qn2 == 0) break;
+        // neither queue full: the candidates are exhausted, drain both
+        const bool drain = qn < 64 && qn2 < 64;
+        // evaluate one batch of a queue (the only call sites of the routines)
+        auto batch = [&](int2 (*qq)[128], int& n, auto& f, long& cnt, long& np) {
+            const int nbatch = n < 64 ? n : 64;
+            const int2 t = qq[wave][lane + 64];
+            if (COOP) {
+                // the whole wave evaluates the queued quartets one after another
+                for (int i = 0; i < nbatch; ++i) evaluate(qq[wave][i], f, np);
+            } else {
+                const int2 q = qq[wave][lane];
+                if (lane < nbatch) evaluate(q, f, np);
+            }
+            cnt += nbatch;
+            fx_wave_sync();
+            qq[wave][lane] = t;
+            n -= nbatch;
+            fx_wave_sync();
+        };
+        if (qn >= 64 || (drain && qn > 0)) batch(queue, qn, fn, nq, npq);
+        if (DUAL && (qn2 >= 64 || (drain && qn2 > 0))) batch(queue2, qn2, fn2, nq2, npq2);
     }
     // deterministic reduction of the 64 lane partials, then one write per element
     const long rowbase = (long)Bs.f0[a] * Sy.n + Bs.f0[d];
@@ -290,31 +308,35 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, long 
             kslot[(long)(Bs.f0[d] + lane % ND) * Sy.n + Bs.f0[a] + lane / ND] = outv[j];
     }
     if (A.times && lane == 0) A.times[u] = (float)(wall_clock64() - t_start);
-    if (A.counters) {
-        long np = npq;
+    auto count = [&](unsigned long long* ctr, long q, long npl) {
+        long np = npl;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) np += __shfl_xor(np, off, 64);
         if (lane == 0) {
-            atomicAdd(A.counters, (unsigned long long)nq);
-            atomicAdd(A.counters + 1, (unsigned long long)np);
-            if (Sy.sym && a != d) atomicAdd(A.counters + 2, (unsigned long long)nq);
+            atomicAdd(ctr, (unsigned long long)q);
+            atomicAdd(ctr + 1, (unsigned long long)np);
+            if (Sy.sym && a != d) atomicAdd(ctr + 2, (unsigned long long)q);
         }
-    }
+    };
+    if (A.counters) count(A.counters, nq, npq);
+    if (DUAL && A.counters2) count(A.counters2, nq2, npq2);
 }
 
 // Kernel-level unit loop: one unit per wave, with an optional XCD-aware remap
 // of workgroups (fx_xcd_remap) so that neighbouring units -- which share
 // density and pair data -- run on one XCD and its L2.  K does not depend on
 // the mapping.
-template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, int NDENS, typename Fn>
-__device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
+template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, int NDENS, bool DUAL = false, typename Fn,
+          typename Fn2>
+__device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn, Fn2 fn2) {
     __shared__ int2 queue[WAVES][128];
+    __shared__ int2 queue2[DUAL ? WAVES : 1][128];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     long blk = blockIdx.x;
     if (A.flags & FX_LAUNCH_XCD) blk = fx_xcd_remap(blk, gridDim.x);
     const long slot_unit = blk * WAVES + wave;
     if (slot_unit >= A.nunits) return;
-    fx_class_unit<LA, LB, LC, LD, COOP, WAVES, NDENS>(A, fn, slot_unit, wave, queue);
+    fx_class_unit<LA, LB, LC, LD, COOP, WAVES, NDENS, DUAL>(A, fn, fn2, slot_unit, wave, queue, queue2);
 }
 
 // Thread variant: one quartet per lane.
@@ -332,23 +354,45 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
     template <int NDENS>                                                                                 \
     __global__ __launch_bounds__(64 * FX_CLASS_WAVES, FX_THREAD_MIN_WAVES_##prec) void                  \
         fx_k_##cls##_##prec(FxClassArgs A) {                                                            \
-        fx_class_body<la, lb, lc, ld, false, FX_CLASS_WAVES, NDENS>(                                    \
-            A, [](const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc, const FxShellRef& rd, \
-                  const FxDevBasis& B, const double* bt, const double* const* P, long n, double* k, int) { \
-                eri_##cls##_##prec<NDENS>(ra, rb, rc, rd, B, bt, P, n, k);                               \
-            });                                                                                          \
+        auto f = [](const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc, const FxShellRef& rd, \
+                    const FxDevBasis& B, const double* bt, const double* const* P, long n, double* k, int) { \
+            eri_##cls##_##prec<NDENS>(ra, rb, rc, rd, B, bt, P, n, k);                                   \
+        };                                                                                               \
+        fx_class_body<la, lb, lc, ld, false, FX_CLASS_WAVES, NDENS>(A, f, f);                            \
     }
+
+// Mixed precision in one pass: each candidate screened once, evaluated by the
+// FP64 or the FP32 routine by its bound (one density).
+#ifndef FX_THREAD_MIN_WAVES_mix
+#define FX_THREAD_MIN_WAVES_mix 1
+#endif
+#define FX_DUAL_KERNEL(la, lb, lc, ld, cls)                                                             \
+    __global__ __launch_bounds__(64 * FX_CLASS_WAVES, FX_THREAD_MIN_WAVES_mix) void                     \
+        fx_k_##cls##_mix(FxClassArgs A) {                                                               \
+        auto f64 = [](const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc, const FxShellRef& rd, \
+                      const FxDevBasis& B, const double* bt, const double* const* P, long n, double* k, int) { \
+            eri_##cls##_f64<1>(ra, rb, rc, rd, B, bt, P, n, k);                                          \
+        };                                                                                               \
+        auto f32 = [](const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc, const FxShellRef& rd, \
+                      const FxDevBasis& B, const double* bt, const double* const* P, long n, double* k, int) { \
+            eri_##cls##_f32<1>(ra, rb, rc, rd, B, bt, P, n, k);                                          \
+        };                                                                                               \
+        fx_class_body<la, lb, lc, ld, false, FX_CLASS_WAVES, 1, true>(A, f64, f32);                      \
+    }
+#define FX_LAUNCH_DUAL(cls)                                                                             \
+    hipLaunchKernelGGL(fx_k_##cls##_mix, dim3((A.nunits + FX_CLASS_WAVES - 1) / FX_CLASS_WAVES),         \
+                       dim3(64 * FX_CLASS_WAVES), 0, st, A)
 
 // Cooperative variant: one quartet per wave, intermediates in LDS.
 #define FX_COOP_KERNEL(la, lb, lc, ld, cls, prec, real)                                                 \
     __global__ __launch_bounds__(64 * FX_COOP_WAVES) void fx_kc_##cls##_##prec(FxClassArgs A) {        \
         __shared__ real lds[FX_COOP_WAVES * coop_##cls##_##prec::NSLOT];                                 \
-        fx_class_body<la, lb, lc, ld, true, FX_COOP_WAVES, 1>(                                          \
-            A, [&](const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc, const FxShellRef& rd, \
-                   const FxDevBasis& B, const double* bt, const double* const* P, long n, double* k, int w) { \
-                eri_##cls##_##prec##_coop(ra, rb, rc, rd, B, bt, P[0], n,                                \
-                                          lds + w * coop_##cls##_##prec::NSLOT, k[0]);                   \
-            });                                                                                          \
+        auto f = [&](const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc, const FxShellRef& rd, \
+                     const FxDevBasis& B, const double* bt, const double* const* P, long n, double* k, int w) { \
+            eri_##cls##_##prec##_coop(ra, rb, rc, rd, B, bt, P[0], n, lds + w * coop_##cls##_##prec::NSLOT,  \
+                                      k[0]);                                                             \
+        };                                                                                               \
+        fx_class_body<la, lb, lc, ld, true, FX_COOP_WAVES, 1>(A, f, f);                                  \
     }
 
 #define FX_LAUNCH_THREAD(cls, prec)                                                                     \
@@ -368,9 +412,14 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
 #define FX_DEFINE_CLASS_KERNELS_BOTH(la, lb, lc, ld, cls)                                               \
     FX_THREAD_KERNEL(la, lb, lc, ld, cls, f64)                                                          \
     FX_THREAD_KERNEL(la, lb, lc, ld, cls, f32)                                                          \
+    FX_DUAL_KERNEL(la, lb, lc, ld, cls)                                                                 \
     FX_COOP_KERNEL(la, lb, lc, ld, cls, f64, double)                                                    \
     FX_COOP_KERNEL(la, lb, lc, ld, cls, f32, float)                                                     \
-    int fx_launch_##cls(int prec32, int variant, FxClassArgs A, hipStream_t st) {              \
+    int fx_launch_##cls(int prec32, int variant, FxClassArgs A, hipStream_t st) {                        \
+        if (A.mode == FX_MODE_DUAL) {                                                                    \
+            FX_LAUNCH_DUAL(cls);                                                                         \
+            return 2;                                                                                    \
+        }                                                                                                \
         if (variant == 1 && A.ndens == 1) {                                                              \
             if (prec32) FX_LAUNCH_COOP(cls, f32); else FX_LAUNCH_COOP(cls, f64);                         \
             return 1;                                                                                    \
@@ -382,7 +431,12 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn) {
 #define FX_DEFINE_CLASS_KERNELS_THREAD(la, lb, lc, ld, cls)                                             \
     FX_THREAD_KERNEL(la, lb, lc, ld, cls, f64)                                                          \
     FX_THREAD_KERNEL(la, lb, lc, ld, cls, f32)                                                          \
+    FX_DUAL_KERNEL(la, lb, lc, ld, cls)                                                                 \
     int fx_launch_##cls(int prec32, int, FxClassArgs A, hipStream_t st) {                                \
+        if (A.mode == FX_MODE_DUAL) {                                                                    \
+            FX_LAUNCH_DUAL(cls);                                                                         \
+            return 2;                                                                                    \
+        }                                                                                                \
         if (prec32) FX_LAUNCH_THREAD(cls, f32); else FX_LAUNCH_THREAD(cls, f64);                         \
         return 0;                                                                                        \
     }

@@ -510,7 +510,7 @@ static int g_flags[81][2];
 static bool g_variant_init = [] {
     for (int c = 0; c < 81; ++c)
         for (int p = 0; p < 2; ++p) {
-            g_variant[c][p] = (fx_class_variants[c] & 1) ? 0 : 1;
+            g_variant[c][p] = (fx_class_variants[c] & 1) ? ((p == 0 && fx_class_dual_default[c]) ? 2 : 0) : 1;
             g_flags[c][p] = 0;
         }
     return true;
@@ -788,12 +788,16 @@ static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
                                             ln.key, ln.bpos, ln.bpartial, ln.total, ln.order, ls, fx_scan_i32);
                         args.order = ln.order;
                     }
-                    for (int pr = 0; pr < nprec; ++pr) {
+                    // mixed precision in one pass (variant 2 on the FP64 entry, one density)
+                    const bool dual = nprec == 2 && c.ndens == 1 && g_variant[cls][0] == 2;
+                    for (int pr = 0; pr < (dual ? 1 : nprec); ++pr) {
                         if (c.rec) args.times = times;
-                        args.mode = c.precision == FX_PREC_MIXED ? (pr ? FX_MODE_MIXED_LO : FX_MODE_MIXED_HI)
-                                                                 : FX_MODE_ALL;
+                        args.mode = dual ? FX_MODE_DUAL
+                                         : c.precision == FX_PREC_MIXED ? (pr ? FX_MODE_MIXED_LO : FX_MODE_MIXED_HI)
+                                                                        : FX_MODE_ALL;
                         args.slot_index = slot_index(c, lb, lc, pr);
                         args.counters = c.counters + (cls * 2 + pr) * 3;
+                        args.counters2 = dual ? c.counters + (cls * 2 + 1) * 3 : nullptr;
                         args.flags = g_flags[cls][pr];
                         if (c.profile) {
                             // events on the stream the kernel is launched on
@@ -1232,8 +1236,9 @@ const char* fx_last_error_message(void) { return g_last_error.c_str(); }
 
 fx_status fx_set_class_variant(int32_t cls, int32_t prec32, int32_t variant) {
     return fx_guard([&] {
-        if (cls < 0 || cls >= 81 || prec32 < 0 || prec32 > 1 || variant < 0 || variant > 1)
-            fx_fail(FX_ERR_INVALID_ARG, "class 0..80, prec32 0..1, variant 0..1");
+        if (cls < 0 || cls >= 81 || prec32 < 0 || prec32 > 1 || variant < 0 || variant > 2)
+            fx_fail(FX_ERR_INVALID_ARG, "class 0..80, prec32 0..1, variant 0..2");
+        if (variant == 2 && prec32 != 0) fx_fail(FX_ERR_INVALID_ARG, "variant 2 is set on the FP64 entry");
         if (!(fx_class_variants[cls] & (1 << variant))) fx_fail(FX_ERR_UNSUPPORTED, "variant not built for this class");
         g_variant[cls][prec32] = variant;
     });

@@ -23,7 +23,9 @@ struct FxPrimPair {
     double p, op, Px, Py, Pz, K;
 };
 
-enum { FX_MODE_ALL = 0, FX_MODE_MIXED_HI = 1, FX_MODE_MIXED_LO = 2 };
+// ALL: every surviving quartet in the kernel's precision; MIXED_HI / _LO: the
+// quartets with beta >= / < the FP32 threshold; DUAL: both, in one kernel.
+enum { FX_MODE_ALL = 0, FX_MODE_MIXED_HI = 1, FX_MODE_MIXED_LO = 2, FX_MODE_DUAL = 3 };
 
 // Basis in the tree's shell order (device pointers).
 struct FxDevBasis {
@@ -84,11 +86,12 @@ struct FxClassArgs {
     int ndens;                        // densities per system (1 or 2)
     unsigned long long* counters;     // [3]: quartets, primitive quartets, quartets that also stand
                                       // for their mirror (symmetric system, a != d) (nullable)
+    unsigned long long* counters2;    // DUAL: the same for the FP32 quartets (nullable)
     float* times;                     // per-unit wall-clock ticks (nullable; timing probes)
 };
 
 // launches one wave per unit; returns the variant launched (0 one quartet
-// per lane, 1 one quartet per wave)
+// per lane, 1 one quartet per wave, 2 one quartet per lane in both precisions)
 #define FX_DECLARE_LAUNCH(cls) int fx_launch_##cls(int prec32, int variant, FxClassArgs A, hipStream_t st);
 typedef int (*fx_class_launcher)(int, int, FxClassArgs, hipStream_t);
 void fx_launch_schwarz(FxDevBasis B, const double* boys, const int2* pairs, long npairs, double* Qn,

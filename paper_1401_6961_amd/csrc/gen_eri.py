@@ -749,6 +749,17 @@ UNPAIRED = {"dddd", "ddds", "ddsd", "dsdd", "sddd"}
 # 17-55% faster than forming the bra-transferred block in private memory,
 # except (dd|dd) FP32 (4% slower).
 FOLD = set(STAGED) - {("dddd", "f32")}
+# Classes whose mixed-precision build screens each candidate once and runs
+# both precisions in one kernel (FX_DUAL_KERNEL) by default: chosen per class
+# on the 1000-atom cluster (both forms measured, one pass kept where at least
+# 2% faster).  It saves the second screening pass; it loses where the FP64
+# and FP32 routines want different register budgets ((dd|dd), the FP32
+# classes with two d shells in the register form).
+DUAL = {"dddp", "ddds", "ddpp", "ddps", "ddsd", "ddsp", "dpdd", "dpds", "dppd", "dpsd", "dpss", "dsdp", "dsds", "dspd",
+        "dsps", "dssd", "dssp", "dsss", "pddd", "pdds", "pdsd", "pdss", "ppdd", "pppp", "ppps", "ppsp", "psdd", "psds",
+        "pspp", "psps", "pssd", "pssp", "psss", "sddd", "sddp", "sdpd", "sdps", "sdsd", "sdsp", "sdss", "spdd", "spds",
+        "sppp", "spps", "spsd", "spsp", "spss", "ssdp", "ssds", "sspd", "sspp", "ssps", "sssd", "sssp", "ssss"}
+
 # With the fold, three FP32 classes with two d shells gain too (4-12%); the
 # other FP32 classes with one or two d shells and the (pp|pd)-type classes
 # stay faster in the register form.
@@ -821,8 +832,12 @@ def main(outdir):
     av = []
     for (a, b, c, d) in classes():
         th, co = variants(a, b, c, d)
-        av.append(str((1 if th else 0) | (2 if co else 0)))
+        av.append(str((1 if th else 0) | (2 if co else 0) | (4 if th else 0)))
+    lines.append("// bit 0: one quartet per lane, bit 1: one quartet per wave, bit 2: both precisions in one pass")
     lines.append("static const int fx_class_variants[81] = {" + ", ".join(av) + "};")
+    dv = ["1" if "".join(LNAME[x] for x in t) in DUAL else "0" for t in classes()]
+    lines.append("// default: mixed precision in one pass (variant 2 for the FP64 half)")
+    lines.append("static const int fx_class_dual_default[81] = {" + ", ".join(dv) + "};")
     path = os.path.join(outdir, "eri_table.h")
     new = "\n".join(lines) + "\n"
     if not os.path.exists(path) or open(path).read() != new:

@@ -70,13 +70,16 @@ def test_invalid_arguments_are_rejected_before_device_work():
 def test_variant_table():
     for cls in range(81):
         av = fx.fx_class_variants_available(cls)
-        assert av in (1, 2, 3)
+        assert av in (5, 7)          # one quartet per lane, and both precisions in one pass, always
         for p in (0, 1):
             v = fx.fx_get_class_variant(cls, p)
             assert av & (1 << v)
-    # (ss|ss) has only the thread form, (dd|dd) both
-    assert fx.fx_class_variants_available(0) == 1
-    assert fx.fx_class_variants_available(80) == 3
+            assert v != 2 or p == 0
+    # (ss|ss) has no one-quartet-per-wave form, (dd|dd) has
+    assert fx.fx_class_variants_available(0) == 5
+    assert fx.fx_class_variants_available(80) == 7
+    with pytest.raises(fx.FxError):
+        fx.fx_set_class_variant(80, 1, 2)    # the one-pass form is selected on the FP64 entry
 
 
 def test_hilbert_curve_is_a_unit_step_path():
