@@ -773,6 +773,8 @@ FOLD |= {("ddpp", "f32"), ("dppd", "f32"), ("ppdd", "f32")}
 # register-form kernels that fit at one or two made them spill and run
 # about three times slower.
 MIN_WAVES = {("dddd", "f64"): 3} | {(c, "f64"): 2 for c in ("ddds", "ddsd", "dsdd", "sddd")}
+# one-pass kernels: one wave except five small classes measured faster at two
+MIN_WAVES.update({(c, "mix"): 2 for c in ("sdsd", "dsds", "dssd", "dsss", "spss")})
 
 
 def variants(la, lb, lc, ld):
@@ -802,7 +804,7 @@ def main(outdir):
         src = ["// Generated by gen_eri.py -- do not edit.", '#include "fx_eri_common.h"', ""]
         src += parts
         kind = "BOTH" if (th and co) else ("THREAD" if th else "COOP")
-        for prec in ("f64", "f32"):
+        for prec in ("f64", "f32", "mix"):
             mw = MIN_WAVES.get((cls, prec), 1)
             if mw > 1:
                 src.append(f"#define FX_THREAD_MIN_WAVES_{prec} {mw}")
