@@ -212,7 +212,7 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
     const bool seg = Sy.cls_off != nullptr;
     long cur = seg ? Sy.cls_off[(long)item * 10 + LB * 3 + LC] : e0;
     const long cend = seg ? Sy.cls_off[(long)item * 10 + LB * 3 + LC + 1] : e1;
-    int kc = 0, maxc = 0, nb = 0, nc = 0, ob = 0, oc = 0;
+    int kc = 0, maxc = 0, nb = 0, nc = 0, ob = 0, oc = 0, jb = 0, jc = 0;
     while (true) {
         // fill: screen candidates until a full batch is queued or none are left
         while (qn < 64 && qn2 < 64) {
@@ -242,20 +242,24 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
                         nc = Bs.leaf_lofs[bc.y * 4 + LC + 1] - oc;
                     }
                     maxc = fx_wave_max(nb * nc);
-                    kc = 0;
+                    kc = jb = jc = 0;
                     cur += 64;
                     continue;
                 }
                 int ok = 0;
                 int b = 0, c = 0;
                 if (kc < nb * nc) {
-                    const int kb = kc / nc;
-                    b = Bs.leaf_lsh[ob + kb];
-                    c = Bs.leaf_lsh[oc + (kc - kb * nc)];
+                    // candidate kc = jb * nc + jc of this lane's (B, C) entry
+                    b = Bs.leaf_lsh[ob + jb];
+                    c = Bs.leaf_lsh[oc + jc];
                     ok = test(b, c);
                 }
                 push(ok, b, c);
                 ++kc;
+                if (++jc == nc) {
+                    jc = 0;
+                    ++jb;
+                }
             }
         }
         fx_wave_sync();
