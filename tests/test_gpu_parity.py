@@ -241,3 +241,26 @@ def test_cooperative_variants(spd5):
     finally:
         for (cls, p), v in saved.items():
             fx.fx_set_class_variant(cls, p, v)
+
+
+def test_one_pass_mixed_matches_two_passes(spd5):
+    """Mixed precision with both precisions in one kernel (variant 2) and in
+    two kernels per class: the same quartets in each precision, K equal to
+    rounding, both within the mixed tolerance of the oracle."""
+    say("gpu: mixed precision, one pass vs two passes per class")
+    Ko, _ = oracle.exchange(spd5, tau=1e-11)
+    saved = {c: fx.fx_get_class_variant(c, 0) for c in range(81)}
+    try:
+        for c in range(81):
+            fx.fx_set_class_variant(c, 0, 2)
+        K1, st1, tree = gpu_exchange(spd5, 1e-11, precision=fx.FX_PREC_MIXED)
+        for c in range(81):
+            fx.fx_set_class_variant(c, 0, 0)
+        K2, st2, _ = gpu_exchange(spd5, 1e-11, tree=tree, precision=fx.FX_PREC_MIXED)
+    finally:
+        for c, v in saved.items():
+            fx.fx_set_class_variant(c, 0, v)
+    assert st1["quartets"] == st2["quartets"] and st1["quartets_fp32"] == st2["quartets_fp32"] > 0
+    assert np.array_equal(st1["class_prec_quartets"], st2["class_prec_quartets"])
+    assert np.abs(K1 - K2).max() <= 1e-12
+    assert np.abs(K1 - Ko).max() <= 1e-7 and np.abs(K2 - Ko).max() <= 1e-7
