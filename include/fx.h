@@ -250,8 +250,12 @@ void fx_costmodel_free(fx_costmodel* m);
 
 /* Kernel variant of a class (cls = ((la*3+lb)*3+lc)*3+ld) and precision
  * (prec32 0/1): 0 = one quartet per lane, 1 = one quartet per wave with the
- * HGP intermediates in LDS.  Chosen by the autotuner; both give the same
- * quartet set and agree to rounding.  Process-wide setting. */
+ * HGP intermediates in LDS, 2 (FP64 entry only) = in mixed precision with one
+ * density, both precisions in one kernel that screens each candidate once
+ * (the FP32 entry is then unused).  Defaults are built in per class and the
+ * autotuner may change them; all variants give the same quartet set and agree
+ * to rounding.  Process-wide setting; FX_ERR_INVALID_ARG for a bad class,
+ * precision or variant, FX_ERR_UNSUPPORTED for a variant not built. */
 fx_status fx_set_class_variant(int32_t cls, int32_t prec32, int32_t variant);
 int32_t fx_get_class_variant(int32_t cls, int32_t prec32);
 /* Launch flags of a class and precision: bit 0 = XCD-aware workgroup remap
@@ -264,7 +268,7 @@ int32_t fx_get_class_launch(int32_t cls, int32_t prec32);
 /* Logical block of hardware workgroup b of nb under the XCD remap (-1 if out
  * of range); host-callable so the mapping can be checked. */
 int64_t fx_xcd_block(int64_t b, int64_t nb);
-/* Bit mask of the variants built for a class (bit 0 thread, bit 1 wave). */
+/* Bit mask of the variants built for a class (bit v = variant v). */
 int32_t fx_class_variants_available(int32_t cls);
 
 /* Device allocator used for all library memory (NULL, NULL restores
