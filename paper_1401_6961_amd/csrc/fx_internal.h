@@ -3,7 +3,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define FX_CLASS_WAVES 4          // waves (work units) per thread-variant workgroup
+// One wave (one K-block unit) per workgroup: units differ widely in work, and
+// a workgroup of several waves holds its slot until its slowest wave ends
+// (4 waves per workgroup: 20.7 s; 1: 17.0 s on the 1000-atom cluster).
+#define FX_CLASS_WAVES 1          // waves (work units) per thread-variant workgroup
 #define FX_COOP_WAVES 2           // waves per cooperative-variant workgroup
 #define FX_MAX_DENS 2             // densities contracted with the same integrals
 
