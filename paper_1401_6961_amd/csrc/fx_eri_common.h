@@ -208,8 +208,11 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
         }
     };
     // Candidate cursor: single-shell leaves read the item's (lb, lc) segment
-    // (leaf index == shell index); larger leaves enumerate b in B, c in C.
+    // (leaf index == shell index); leaves with at most one shell per l map
+    // (B, C) straight to (b, c), one candidate per entry; other leaves
+    // enumerate b in B, c in C.
     const bool seg = Sy.cls_off != nullptr;
+    const int* __restrict__ one = Bs.leaf_one;
     long cur = seg ? Sy.cls_off[(long)item * 10 + LB * 3 + LC] : e0;
     const long cend = seg ? Sy.cls_off[(long)item * 10 + LB * 3 + LC + 1] : e1;
     int kc = 0, maxc = 0, nb = 0, nc = 0, ob = 0, oc = 0, jb = 0, jc = 0;
@@ -226,6 +229,19 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
                     b = bc.x;
                     c = bc.y;
                     ok = test(b, c);
+                }
+                push(ok, b, c);
+                cur += 64;
+            } else if (one) {
+                if (cur >= cend) break;
+                const long e = cur + lane;
+                int ok = 0;
+                int b = 0, c = 0;
+                if (e < cend) {
+                    const int2 bc = Sy.bc[e];
+                    b = one[bc.x * 3 + LB];
+                    c = one[bc.y * 3 + LC];
+                    if (b >= 0 && c >= 0) ok = test(b, c);
                 }
                 push(ok, b, c);
                 cur += 64;

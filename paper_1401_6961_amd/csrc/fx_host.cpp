@@ -423,6 +423,16 @@ static void build_tree(const fx_shells* s, const fx_tree_opts* opts, hipStream_t
     }
     T->leaf_lofs = lofs;
     T->single_shell_leaves = (int)leaf.sL.size() == S;
+    // at most one shell per leaf and l (e.g. one atom of an s+p+d basis per
+    // leaf): the class kernels map a leaf straight to its shell
+    std::vector<int> one(nleaf * 3, -1);
+    bool one_per_l = true;
+    for (int A = 0; A < nleaf && one_per_l; ++A)
+        for (int L = 0; L < 3; ++L) {
+            const int k = lofs[A * 4 + L + 1] - lofs[A * 4 + L];
+            if (k > 1) one_per_l = false;
+            else if (k == 1) one[A * 3 + L] = lsh[lofs[A * 4 + L]];
+        }
 
     T->arena = new DevArena(st, true);
     DevArena& A = *T->arena;
@@ -438,6 +448,7 @@ static void build_tree(const fx_shells* s, const fx_tree_opts* opts, hipStream_t
     B.coefs = upload(A, co);
     B.leaf_lofs = upload(A, lofs);
     B.leaf_lsh = upload(A, lsh.empty() ? std::vector<int>{0} : lsh);
+    B.leaf_one = one_per_l ? upload(A, one) : nullptr;
     T->boys = upload(A, boys_table());
     // primitive pairs of every ordered pair of primitives
     {

@@ -43,6 +43,8 @@ struct FxDevBasis {
     const double* Qn;     // [S*S] ||Q_ab||_F
     const int* leaf_lofs; // [nleaf*4] per leaf: offsets of its l=0,1,2 shell lists, then end
     const int* leaf_lsh;  // shell indices grouped per leaf and l
+    const int* leaf_one;  // [nleaf*3] per leaf and l: its one shell of that l (-1: none);
+                          // null when some leaf holds two shells of one l
     long ntprim;          // total primitives Nt
     const FxPrimPair* pp; // [Nt*Nt] primitive-pair records, (global prim i, global prim j)
 };
