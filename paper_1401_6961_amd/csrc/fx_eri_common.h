@@ -150,9 +150,13 @@ __device__ __forceinline__ double fx_comp_factor(int l, int k) {
 // DUAL (mixed precision in one pass): each candidate is screened once and
 // queued for the FP64 routine `fn` (beta >= thr) or the FP32 routine `fn2`
 // (beta < thr); both accumulate into the same FP64 K block.
+// Candidate queue of one wave in LDS: a fill step adds at most 128 entries to
+// a queue holding at most 63, and a batch takes 64 from its front.
+constexpr int FX_QCAP = 192;
+
 template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, int NDENS, bool DUAL, typename Fn, typename Fn2>
 __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 fn2, long slot_unit, int wave,
-                                              int2 (*queue)[128], int2 (*queue2)[128]) {
+                                              int2 (*queue)[FX_QCAP], int2 (*queue2)[FX_QCAP]) {
     static_assert(!COOP || NDENS == 1, "the one-quartet-per-wave form contracts one density");
     static_assert(!COOP || !DUAL, "the one-quartet-per-wave form runs one precision");
     constexpr int NA = fx_ncart(LA), ND = fx_ncart(LD);
@@ -233,18 +237,28 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
                 push(ok, b, c);
                 cur += 64;
             } else if (one) {
+                // two groups of 64 entries per step: their gathers overlap;
+                // pushed in entry order
                 if (cur >= cend) break;
                 const long e = cur + lane;
-                int ok = 0;
-                int b = 0, c = 0;
-                if (e < cend) {
-                    const int2 bc = Sy.bc[e];
-                    b = one[bc.x * 3 + LB];
-                    c = one[bc.y * 3 + LC];
-                    if (b >= 0 && c >= 0) ok = test(b, c);
+                const bool v0 = e < cend, v1 = e + 64 < cend;
+                int2 bc0 = make_int2(0, 0), bc1 = make_int2(0, 0);
+                if (v0) bc0 = Sy.bc[e];
+                if (v1) bc1 = Sy.bc[e + 64];
+                int b0 = -1, c0 = -1, b1 = -1, c1 = -1;
+                if (v0) {
+                    b0 = one[bc0.x * 3 + LB];
+                    c0 = one[bc0.y * 3 + LC];
                 }
-                push(ok, b, c);
-                cur += 64;
+                if (v1) {
+                    b1 = one[bc1.x * 3 + LB];
+                    c1 = one[bc1.y * 3 + LC];
+                }
+                const int ok0 = (b0 >= 0 && c0 >= 0) ? test(b0, c0) : 0;
+                const int ok1 = (b1 >= 0 && c1 >= 0) ? test(b1, c1) : 0;
+                push(ok0, b0, c0);
+                push(ok1, b1, c1);
+                cur += 128;
             } else {
                 if (kc >= maxc) {
                     if (cur >= cend) break;
@@ -283,9 +297,8 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
         // neither queue full: the candidates are exhausted, drain both
         const bool drain = qn < 64 && qn2 < 64;
         // evaluate one batch of a queue (the only call sites of the routines)
-        auto batch = [&](int2 (*qq)[128], int& n, auto& f, long& cnt, long& np) {
+        auto batch = [&](int2 (*qq)[FX_QCAP], int& n, auto& f, long& cnt, long& np) {
             const int nbatch = n < 64 ? n : 64;
-            const int2 t = qq[wave][lane + 64];
             if (COOP) {
                 // the whole wave evaluates the queued quartets one after another
                 for (int i = 0; i < nbatch; ++i) evaluate(qq[wave][i], f, np);
@@ -295,7 +308,13 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
             }
             cnt += nbatch;
             fx_wave_sync();
+            // move the rest (at most 127) to the front; lane i reads slots
+            // 64 + i and 128 + i and writes slots i and 64 + i, so no lane
+            // overwrites a slot another lane still has to read
+            const int2 t = qq[wave][lane + 64];
+            const int2 t2 = qq[wave][lane + 128];
             qq[wave][lane] = t;
+            qq[wave][lane + 64] = t2;
             n -= nbatch;
             fx_wave_sync();
         };
@@ -349,8 +368,8 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
 template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, int NDENS, bool DUAL = false, typename Fn,
           typename Fn2>
 __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn, Fn2 fn2) {
-    __shared__ int2 queue[WAVES][128];
-    __shared__ int2 queue2[DUAL ? WAVES : 1][128];
+    __shared__ int2 queue[WAVES][FX_QCAP];
+    __shared__ int2 queue2[DUAL ? WAVES : 1][FX_QCAP];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     long blk = blockIdx.x;
     if (A.flags & FX_LAUNCH_XCD) blk = fx_xcd_remap(blk, gridDim.x);
