@@ -150,9 +150,11 @@ __device__ __forceinline__ double fx_comp_factor(int l, int k) {
 // DUAL (mixed precision in one pass): each candidate is screened once and
 // queued for the FP64 routine `fn` (beta >= thr) or the FP32 routine `fn2`
 // (beta < thr); both accumulate into the same FP64 K block.
-// Candidate queue of one wave in LDS: a fill step adds at most 128 entries to
-// a queue holding at most 63, and a batch takes 64 from its front.
-constexpr int FX_QCAP = 192;
+// Candidate queue of one wave in LDS: a fill step screens up to FX_FILL_GROUPS
+// groups of 64 entries and adds their survivors to a queue holding at most
+// 63; a batch takes 64 from its front.
+constexpr int FX_FILL_GROUPS = 3;
+constexpr int FX_QCAP = 64 * (FX_FILL_GROUPS + 1);
 
 template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, int NDENS, bool DUAL, typename Fn, typename Fn2>
 __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 fn2, long slot_unit, int wave,
@@ -237,28 +239,30 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
                 push(ok, b, c);
                 cur += 64;
             } else if (one) {
-                // two groups of 64 entries per step: their gathers overlap;
-                // pushed in entry order
+                // FX_FILL_GROUPS groups of 64 entries per step: their gathers
+                // overlap; pushed in entry order
                 if (cur >= cend) break;
-                const long e = cur + lane;
-                const bool v0 = e < cend, v1 = e + 64 < cend;
-                int2 bc0 = make_int2(0, 0), bc1 = make_int2(0, 0);
-                if (v0) bc0 = Sy.bc[e];
-                if (v1) bc1 = Sy.bc[e + 64];
-                int b0 = -1, c0 = -1, b1 = -1, c1 = -1;
-                if (v0) {
-                    b0 = one[bc0.x * 3 + LB];
-                    c0 = one[bc0.y * 3 + LC];
+                constexpr int G = FX_FILL_GROUPS;
+                int2 bcg[G];
+                int bg[G], cg[G], okg[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    bcg[g] = make_int2(0, 0);
+                    if (cur + 64 * g + lane < cend) bcg[g] = Sy.bc[cur + 64 * g + lane];
                 }
-                if (v1) {
-                    b1 = one[bc1.x * 3 + LB];
-                    c1 = one[bc1.y * 3 + LC];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    bg[g] = cg[g] = -1;
+                    if (cur + 64 * g + lane < cend) {
+                        bg[g] = one[bcg[g].x * 3 + LB];
+                        cg[g] = one[bcg[g].y * 3 + LC];
+                    }
                 }
-                const int ok0 = (b0 >= 0 && c0 >= 0) ? test(b0, c0) : 0;
-                const int ok1 = (b1 >= 0 && c1 >= 0) ? test(b1, c1) : 0;
-                push(ok0, b0, c0);
-                push(ok1, b1, c1);
-                cur += 128;
+#pragma unroll
+                for (int g = 0; g < G; ++g) okg[g] = (bg[g] >= 0 && cg[g] >= 0) ? test(bg[g], cg[g]) : 0;
+#pragma unroll
+                for (int g = 0; g < G; ++g) push(okg[g], bg[g], cg[g]);
+                cur += 64 * G;
             } else {
                 if (kc >= maxc) {
                     if (cur >= cend) break;
@@ -308,13 +312,14 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
             }
             cnt += nbatch;
             fx_wave_sync();
-            // move the rest (at most 127) to the front; lane i reads slots
-            // 64 + i and 128 + i and writes slots i and 64 + i, so no lane
+            // move the rest (at most FX_QCAP - 65) to the front; lane i reads
+            // slots 64 (k + 1) + i and writes slots 64 k + i, so no lane
             // overwrites a slot another lane still has to read
-            const int2 t = qq[wave][lane + 64];
-            const int2 t2 = qq[wave][lane + 128];
-            qq[wave][lane] = t;
-            qq[wave][lane + 64] = t2;
+            int2 t[FX_FILL_GROUPS];
+#pragma unroll
+            for (int k = 0; k < FX_FILL_GROUPS; ++k) t[k] = qq[wave][64 * (k + 1) + lane];
+#pragma unroll
+            for (int k = 0; k < FX_FILL_GROUPS; ++k) qq[wave][64 * k + lane] = t[k];
             n -= nbatch;
             fx_wave_sync();
         };
