@@ -36,12 +36,15 @@ def lib():
         L.fxo_exchange_blocks.argtypes = shells + [f64p, ctypes.c_double, f64p, f64p, ctypes.c_int,
                                                    i32p, f64p, f64p]
         L.fxo_bound_matrix.argtypes = [ctypes.c_int, i32p, f64p, f64p, ctypes.c_double, f64p]
+        L.fxo_exchange_leafblock.argtypes = shells + [f64p, ctypes.c_double, ctypes.c_int, f64p, f64p]
         L.fxo_count.argtypes = [ctypes.c_int, i32p, i32p, f64p, f64p, ctypes.c_double, f64p,
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         for f in ("fxo_norm_coefs", "fxo_eri_quartet", "fxo_eri_tensor", "fxo_schwarz", "fxo_pnorm",
-                  "fxo_exchange", "fxo_exchange_blocks", "fxo_bound_matrix", "fxo_count"):
+                  "fxo_exchange", "fxo_exchange_blocks", "fxo_bound_matrix", "fxo_count", "fxo_exchange_leafblock"):
             getattr(L, f).restype = ctypes.c_int
         L.fxo_num_threads.restype = ctypes.c_int
+        L.fxo_set_threads.argtypes = [ctypes.c_int]
+        L.fxo_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -113,6 +116,22 @@ def exchange(s, P=None, tau=None):
     return K.reshape(n, n), {"quartets": int(st[0]), "near_threshold": int(st[1]), "prim_quartets": int(st[2])}
 
 
+def exchange_leafblock(s, leaf_max=10, P=None, tau=None):
+    """K under the paper's leaf rule: shells in the given order bisected into
+    leaves of at most leaf_max functions, every quartet of a kept leaf task
+    computed.  Returns K and stats (quartets, near-threshold leaf tasks, kept
+    leaf tasks, leaves)."""
+    P = s.P if P is None else P
+    tau = s.tau if tau is None else tau
+    n = s.nbf
+    K = np.zeros(n * n)
+    st = np.zeros(4)
+    _check(lib().fxo_exchange_leafblock(*_sh(s), np.ascontiguousarray(P, np.float64), float(tau), int(leaf_max), K,
+                                        st), "exchange_leafblock")
+    return K.reshape(n, n), {"quartets": int(st[0]), "near_threshold": int(st[1]), "leaf_tasks": int(st[2]),
+                             "leaves": int(st[3])}
+
+
 def exchange_blocks(s, pairs, P=None, tau=None, Qn=None, Pn=None):
     """K blocks for the requested shell pairs (a, d); returns a list of arrays."""
     P = s.P if P is None else P
@@ -160,3 +179,7 @@ def count(s, tau=None, Qn=None, Pn=None, P=None):
 
 def num_threads() -> int:
     return int(lib().fxo_num_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().fxo_set_threads(int(n))

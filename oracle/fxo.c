@@ -527,6 +527,98 @@ int fxo_exchange(int nshell, const int32_t* l, const int32_t* nprim, const doubl
 }
 
 /*
+ * The paper's leaf rule (Section V: the recursion ends at blocks of at most
+ * ten functions, which are evaluated whole).  The basis, in the given shell
+ * order, is bisected as in Eq. (1): a block of shells is split at the shell
+ * boundary nearest its function midpoint (the lower one on a tie) until it
+ * holds at most leaf_max functions or a single shell.  A leaf task
+ * (A,B,C,D) is kept iff its block bound of Eq. (8), in squared norms,
+ *     (Qsq_AB * Qsq_CD) * Psq_BC * (1 + 1e-12) > tau^2,
+ * with Qsq_AB the sum of Qn_ab^2 over the shell pairs of the two blocks
+ * (a ascending, then b) and Psq likewise from Pn.  Every shell quartet of a
+ * kept task is computed, whatever its own bound.  The block norms of the
+ * enclosing tasks are no smaller, so the leaf test alone decides.
+ * stats (nullable): [0] computed quartets, [1] leaf tasks whose bound lies
+ * within 1e-10 relative of the threshold, [2] kept leaf tasks, [3] leaves.
+ */
+static int leaf_split(const int* fp, int lo, int hi, int leaf_max, int* lo_out, int nl) {
+    if (fp[hi] - fp[lo] <= leaf_max || hi - lo == 1) {
+        lo_out[nl] = lo;
+        return nl + 1;
+    }
+    double mid = 0.5 * (double)(fp[lo] + fp[hi]);
+    int best = lo + 1;
+    double bd = 1e300;
+    for (int m = lo + 1; m < hi; ++m) {
+        double dd = fabs((double)fp[m] - mid);
+        if (dd < bd) { bd = dd; best = m; }
+    }
+    nl = leaf_split(fp, lo, best, leaf_max, lo_out, nl);
+    return leaf_split(fp, best, hi, leaf_max, lo_out, nl);
+}
+
+int fxo_exchange_leafblock(int nshell, const int32_t* l, const int32_t* nprim, const double* center,
+                           const double* exps, const double* coefs, const double* P, double tau, int leaf_max,
+                           double* K, double* stats) {
+    obasis B;
+    if (leaf_max < 1) return -1;
+    if (make_basis(&B, nshell, l, nprim, center, exps, coefs)) return -1;
+    int S = nshell, n = B.nbf;
+    double* Qn = (double*)malloc(sizeof(double) * (size_t)S * S);
+    double* Pn = (double*)malloc(sizeof(double) * (size_t)S * S);
+    schwarz_norms(&B, Qn);
+    fxo_pnorm(S, l, P, Pn);
+    int* fp = (int*)malloc(sizeof(int) * (S + 1));
+    fp[0] = 0;
+    for (int s = 0; s < S; ++s) fp[s + 1] = fp[s] + ncart(l[s]);
+    int* lo = (int*)malloc(sizeof(int) * (S + 1));
+    int NL = leaf_split(fp, 0, S, leaf_max, lo, 0);
+    lo[NL] = S;
+    double* Qsq = (double*)malloc(sizeof(double) * (size_t)NL * NL);
+    double* Psq = (double*)malloc(sizeof(double) * (size_t)NL * NL);
+    for (int X = 0; X < NL; ++X)
+        for (int Y = 0; Y < NL; ++Y) {
+            double q = 0.0, pp = 0.0;
+            for (int a = lo[X]; a < lo[X + 1]; ++a)
+                for (int b = lo[Y]; b < lo[Y + 1]; ++b) {
+                    double v = Qn[(size_t)a * S + b], w = Pn[(size_t)a * S + b];
+                    q += v * v;
+                    pp += w * w;
+                }
+            Qsq[(size_t)X * NL + Y] = q;
+            Psq[(size_t)X * NL + Y] = pp;
+        }
+    memset(K, 0, sizeof(double) * (size_t)n * n);
+    const double tau2 = tau * tau;
+    double nq = 0, nnear = 0, nkept = 0;
+#pragma omp parallel for schedule(dynamic) reduction(+ : nq, nnear, nkept)
+    for (int A = 0; A < NL; ++A) {
+        double buf[ONC * ONC * ONC * ONC];
+        for (int D = 0; D < NL; ++D)
+            for (int Bk = 0; Bk < NL; ++Bk)
+                for (int C = 0; C < NL; ++C) {
+                    double b2 = (Qsq[(size_t)A * NL + Bk] * Qsq[(size_t)C * NL + D]) * Psq[(size_t)Bk * NL + C];
+                    double t = b2 * (1.0 + 1e-12);
+                    if (tau > 0.0 && fabs(t / tau2 - 1.0) < 1e-10) nnear += 1;
+                    if (!(t > tau2)) continue;
+                    nkept += 1;
+                    for (int a = lo[A]; a < lo[A + 1]; ++a)
+                        for (int d = lo[D]; d < lo[D + 1]; ++d)
+                            for (int b = lo[Bk]; b < lo[Bk + 1]; ++b)
+                                for (int c = lo[C]; c < lo[C + 1]; ++c) {
+                                    const oshell *Sa = &B.sh[a], *Sb = &B.sh[b], *Sc = &B.sh[c], *Sd = &B.sh[d];
+                                    eri_quartet(Sa, Sb, Sc, Sd, 0, buf);
+                                    contract(Sa, Sb, Sc, Sd, buf, P, n, K + (size_t)Sa->f0 * n, n, Sd->f0);
+                                    nq += 1;
+                                }
+                }
+    }
+    if (stats) { stats[0] = nq; stats[1] = nnear; stats[2] = nkept; stats[3] = NL; }
+    free(Qsq); free(Psq); free(lo); free(fp); free(Qn); free(Pn); free(B.sh);
+    return 0;
+}
+
+/*
  * Sampled K blocks: for each requested shell pair (a,d) the na x nd block
  * of the screened K, out concatenated block after block (row-major each).
  * Qn/Pn: caller-provided shell norms (from fxo_schwarz / fxo_pnorm).
@@ -649,6 +741,15 @@ int fxo_count(int nshell, const int32_t* l, const int32_t* nprim, const double* 
     *near_total = nn;
     free(part); free(ord);
     return 0;
+}
+
+/* Threads the oracle's parallel loops use (OpenMP); n < 1 leaves it unchanged. */
+void fxo_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 int fxo_num_threads(void) {

@@ -427,3 +427,105 @@ def test_density_block_norms_match_numpy(spd):
             ref = max(np.linalg.norm(blk), np.linalg.norm(blkT))
             assert abs(Pn[b, c] - ref) <= 1e-14 * ref
     assert np.array_equal(Pn, Pn.T)
+
+
+def _culled_beta_sum(s, tau, Qn, Pn):
+    """Shell-block sum of beta = (Q_ab Q_cd) P_bc over the culled quartets
+    (beta <= tau), from the Schwarz and density norm tables alone, expanded
+    to the function block of (a, d)."""
+    S = s.nshell
+    beta = (Qn[:, :, None, None] * Qn[None, None, :, :]) * Pn[None, :, :, None]   # [a, b, c, d]
+    Es = np.where(beta <= tau, beta, 0.0).sum(axis=(1, 2))
+    off = np.concatenate([[0], np.cumsum([synthetic.NCART[x] for x in s.l])])
+    E = np.zeros((s.nbf, s.nbf))
+    for a in range(S):
+        for d in range(S):
+            E[off[a]:off[a + 1], off[d]:off[d + 1]] = Es[a, d]
+    return E, beta
+
+
+@pytest.mark.parametrize("tau", [1e-8, 1e-6, 1e-4])
+def test_bound_matrix_is_the_culled_beta_sum(cube10, tau):
+    """The other side of the culling pin (Eq. 8 and the sub-multiplicativity
+    argument after it): E is exactly the sum of the bounds of the culled
+    quartets, so an E that drops the density factor, counts surviving
+    quartets or sums every quartet fails here even though it would still
+    bound |K_tau - K_full|."""
+    s = cube10[0]
+    Qn = oracle.schwarz(s)
+    Pn = oracle.pnorm(s, s.P)
+    E = oracle.bound_matrix(s, tau, Qn=Qn, Pn=Pn)
+    ref, beta = _culled_beta_sum(s, tau, Qn, Pn)
+    assert np.any(beta <= tau) and np.any(beta > tau)
+    assert np.all(np.abs(E - ref) <= 1e-12 * np.maximum(ref, 1e-300))
+
+
+def test_bound_matrix_limits(cube10):
+    """Below the smallest bound nothing is culled (E = 0); above the largest
+    everything is, and E is the full sum over (b, c) of (Q_ab Q_cd) P_bc."""
+    s = cube10[0]
+    Qn = oracle.schwarz(s)
+    Pn = oracle.pnorm(s, s.P)
+    beta = (Qn[:, :, None, None] * Qn[None, None, :, :]) * Pn[None, :, :, None]
+    pos = beta[beta > 0]
+    assert np.all(oracle.bound_matrix(s, 0.5 * pos.min(), Qn=Qn, Pn=Pn) == 0.0)
+    E = oracle.bound_matrix(s, 2.0 * beta.max(), Qn=Qn, Pn=Pn)
+    full = np.einsum("ab,cd,bc->ad", Qn, Qn, Pn)
+    off = np.concatenate([[0], np.cumsum([synthetic.NCART[x] for x in s.l])])
+    for a in range(s.nshell):
+        for d in range(s.nshell):
+            blk = E[off[a]:off[a + 1], off[d]:off[d + 1]]
+            assert np.all(np.abs(blk - full[a, d]) <= 1e-12 * full[a, d])
+
+
+@pytest.mark.parametrize("sep", [20.0, 60.0, 200.0])
+def test_schwarz_far_pair_shortcut(sep):
+    """The oracle's Schwarz table skips the diagonal integral of a pair whose
+    Gaussian-product exponent mu R^2 is at least 575 for every primitive
+    pair (the integral, proportional to exp(-2 mu R^2), is below the FP64
+    range there).  Each table entry must equal the square root of the sum of
+    the diagonal integrals evaluated directly, on both sides of the cut."""
+    shells = [(0, [0.0, 0.0, 0.0], [0.5, 2.0], [0.6, 0.4]),
+              (1, [sep, 0.0, 0.0], [0.4], [1.0]),
+              (2, [0.0, sep, 0.3], [0.9], [1.0])]
+    s = custom(shells)
+    Qn = oracle.schwarz(s)
+    cut = 0
+    for a in range(3):
+        for b in range(3):
+            I = oracle.eri_quartet(s, a, b, a, b)
+            na, nb = I.shape[0], I.shape[1]
+            diag = np.array([I[i, j, i, j] for i in range(na) for j in range(nb)])
+            ref = math.sqrt(np.maximum(diag, 0.0).sum())
+            assert abs(Qn[a, b] - ref) <= 1e-13 * ref + 1e-300, (a, b, Qn[a, b], ref)
+            mu_r2 = min(x * y / (x + y) for x in shells[a][2] for y in shells[b][2]) * \
+                float(np.sum((np.array(shells[a][1]) - np.array(shells[b][1])) ** 2))   # centres in bohr
+            if mu_r2 >= 575.0:
+                assert Qn[a, b] == 0.0
+                cut += 1
+    assert cut > 0 or sep < 50.0
+
+
+@pytest.mark.parametrize("tau", [1e-8, 1e-6])
+def test_leafblock_rule_limits_and_bounds(cube10, tau):
+    """The paper-literal leaf rule (whole leaf blocks computed): with leaves
+    of single shells it is the shell-level rule; with one leaf holding the
+    whole basis it is brute force; in between it computes a superset of the
+    shell-level quartets (a block norm bounds its sub-blocks), so its K lies
+    within the bound matrix of the shell-level culled work."""
+    s, Kf, stf = cube10
+    Ks, sts = oracle.exchange(s, tau=tau)
+    K1, st1 = oracle.exchange_leafblock(s, 1, tau=tau)
+    assert st1["near_threshold"] == 0 and st1["leaves"] == s.nshell
+    assert st1["quartets"] == sts["quartets"]
+    assert np.abs(K1 - Ks).max() <= 1e-14 * np.abs(Ks).max()
+    Kall, stall = oracle.exchange_leafblock(s, s.nbf, tau=tau)
+    assert stall["leaves"] == 1 and stall["quartets"] == stf["quartets"]
+    assert np.abs(Kall - Kf).max() <= 1e-14 * np.abs(Kf).max()
+    E = oracle.bound_matrix(s, tau)
+    for leaf in (4, 10):
+        Kb, stb = oracle.exchange_leafblock(s, leaf, tau=tau)
+        assert stb["near_threshold"] == 0
+        assert sts["quartets"] <= stb["quartets"] <= stf["quartets"]
+        assert np.all(np.abs(Kb - Ks) <= E * (1 + 1e-9) + 1e-15)
+        assert np.abs(Kb - Kb.T).max() <= 1e-13 * np.abs(Kb).max()
