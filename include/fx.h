@@ -110,17 +110,34 @@ typedef struct fx_costmodel fx_costmodel;
  *   FX_SYM_OFF:  every K block is built (any P). */
 typedef enum fx_symmetry { FX_SYM_AUTO = 0, FX_SYM_OFF = 1 } fx_symmetry;
 
+/* What a surviving leaf task of the traversal computes.
+ *   FX_LEAF_SHELL: every shell quartet inside it is tested with the
+ *                  shell-level bound of Eq. (8) (default): the computed set
+ *                  is exactly {q : beta_q > tau}, independent of the tree;
+ *   FX_LEAF_BLOCK: every shell quartet inside it is computed, as the paper's
+ *                  implementation evaluates whole leaf blocks (Section V);
+ *                  the set then depends on the leaf size. */
+typedef enum fx_leaf_screen { FX_LEAF_SHELL = 0, FX_LEAF_BLOCK = 1 } fx_leaf_screen;
+
+/* Options of an exchange call.  Fill with fx_exchange_opts_init() and then
+ * change fields: an all-zero struct is NOT the defaults (alpha = 0 would
+ * return K = beta*K, and fp32_threshold = 0 would run every quartet in FP64). */
 typedef struct fx_exchange_opts {
     int32_t precision;          /* fx_precision, default FX_PREC_FP64        */
     double fp32_threshold;      /* default 1e-5                              */
     int32_t schedule;           /* fx_schedule, default FX_SCHED_BOUND       */
     const fx_costmodel* costmodel;
     double alpha, beta;         /* K <- alpha*K_x + beta*K; default 1, 0     */
-    int64_t max_frontier_entries; /* traversal chunking threshold, 0 = auto  */
-    int32_t profile;            /* 1: time every class-kernel launch with HIP events on `stream` */
-    int32_t use_graph;          /* 1: capture the class-kernel launch sequence in a hipGraph and launch it */
+    int64_t max_frontier_entries; /* entry capacity of a traversal level; 0 = sized from earlier calls */
+    int32_t profile;            /* 1: time every class-kernel launch with HIP events on `stream` (waits) */
+    int32_t use_graph;          /* 1: capture the whole call once in a hipGraph and replay the capture on later
+                                   calls with the same tree(s), P, K, tau and options */
     int32_t symmetry;           /* fx_symmetry, default FX_SYM_AUTO          */
+    int32_t leaf_screen;        /* fx_leaf_screen, default FX_LEAF_SHELL     */
 } fx_exchange_opts;
+
+/* Fill *o with the defaults documented above. */
+void fx_exchange_opts_init(fx_exchange_opts* o);
 
 /* Statistics of one fx_exchange_ex call (valid when the call returns). */
 #define FX_STATS_MAX_LEVELS 32
@@ -145,6 +162,16 @@ typedef struct fx_stats {
     int64_t quartets_covered;                    /* ordered quartets with beta > tau that K accounts for
                                                     (evaluated ones plus the mirrors they stand for) */
     int32_t symmetric_systems;                   /* systems built on the symmetric path */
+    /* Traversal partition (Eqs. 7a-d): sums of |A||B||C||D| (function counts
+     * of the four tree nodes) over [0] the surviving leaf tasks, [1] the
+     * culled tasks, [2] the tasks skipped because their mirror (D,C,B,A) is
+     * traversed (symmetric form).  Every task of the product of the four
+     * trees is in exactly one set, so the sum is n^4 per system (modulo
+     * 2^64). */
+    int64_t partition[3];
+    int32_t overflow;                            /* 1: a traversal level exceeded its capacity and the call
+                                                    split its K rows and ran them again (K is complete) */
+    int64_t workspace_bytes;                     /* device workspace of the call */
 } fx_stats;
 
 /* Build the basis-function tree for a set of shells: normalisation, shell
@@ -158,11 +185,24 @@ fx_status fx_build_quadtree(const fx_shells* shells, const fx_tree_opts* opts, v
 /* K <- K_x(P) with the defaults of fx_exchange_ex (FP64, alpha 1, beta 0).
  * P, K: device, n x n row-major FP64 (n = fx_nbf(tree)), caller order.
  * tau >= 0 (tau = 0 culls only exactly-zero bounds).  K is overwritten; P
- * must not alias K.  Work is ordered on `stream`; the call returns when K
- * is complete (the traversal reads frontier sizes back to the host). */
+ * must not alias K.
+ *
+ * Asynchronous: the work is enqueued on `stream` and the call returns
+ * without waiting for it; P must stay unchanged and K unread until the
+ * stream reaches that point.  Every size the traversal produces stays on the
+ * device.  Buffers are sized from the sizes earlier calls on the same tree
+ * needed (with a 25% margin); the first call on a tree learns them in a
+ * traversal-only pass, for which it waits.  If a later call needs more than
+ * its buffers hold, that call writes NaN into K (and, when it waits for
+ * statistics, redoes the work in K row ranges and returns the right K); the
+ * next call uses the larger sizes.  Calls on one tree are serialised on the
+ * host; the device work of calls on different streams may overlap. */
 fx_status fx_exchange(const fx_tree* tree, const double* P, double tau, double* K, void* stream);
 
-/* As fx_exchange with options and statistics (stats may be NULL). */
+/* As fx_exchange with options and statistics.  stats == NULL (and no
+ * opts.profile): asynchronous as fx_exchange.  stats != NULL: the call waits
+ * for its result, fills *stats, and never returns a NaN K for lack of
+ * buffer space (it splits the traversal into K row ranges instead). */
 fx_status fx_exchange_ex(const fx_tree* tree, const double* P, double tau, double* K,
                          const fx_exchange_opts* opts, fx_stats* stats, void* stream);
 
@@ -247,6 +287,11 @@ fx_status fx_costmodel_predict(const fx_costmodel* m, const float* feats, int64_
 fx_status fx_costmodel_loss_grad(const fx_costmodel* m, const float* feats, const float* log2_ns, int64_t n,
                                  float* loss, float* grad, void* stream);
 void fx_costmodel_free(fx_costmodel* m);
+/* Serialise a model (parameters and normalisation, binary32) to a file, and
+ * load one back; the loaded model predicts bitwise as the saved one.  Load
+ * returns FX_ERR_INVALID_ARG for a missing, truncated or foreign file. */
+fx_status fx_costmodel_save(const fx_costmodel* m, const char* path);
+fx_status fx_costmodel_load(const char* path, fx_costmodel** out);
 
 /* Kernel variant of a class (cls = ((la*3+lb)*3+lc)*3+ld) and precision
  * (prec32 0/1): 0 = one quartet per lane, 1 = one quartet per wave with the

@@ -29,20 +29,30 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 
 
 def _sources():
-    srcs = [os.path.join(CSRC, f) for f in ("fx_kernels.hip", "fx_host.cpp", "fx_costmodel.hip")
+    srcs = [os.path.join(CSRC, f) for f in ("fx_kernels.hip", "fx_host.cpp", "fx_exec.cpp", "fx_costmodel.hip")
             if os.path.exists(os.path.join(CSRC, f))]
     srcs += sorted(os.path.join(GEN, f) for f in os.listdir(GEN) if f.endswith(".hip"))
     return srcs
 
 
-def _headers_digest():
+# Headers a generated class-kernel source can include (directly or through
+# fx_eri_common.h); every other source may include any header.
+CLASS_HEADERS = ("fx_eri_common.h", "fx_internal.h")
+
+
+def _headers_digest(only=None):
     h = hashlib.sha256()
     for d in (CSRC, GEN, os.path.join(ROOT, "include")):
         for f in sorted(os.listdir(d)):
-            if f.endswith(".h"):
+            if f.endswith(".h") and (only is None or f in only):
                 h.update(f.encode())
                 h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()
+
+
+def _digest_for(src, full, classes):
+    """Class-kernel sources depend on the kernel-template headers only."""
+    return classes if os.path.basename(src).startswith("eri_") else full
 
 
 def _compile(src, hdr_digest, incremental):
@@ -69,13 +79,13 @@ def build(incremental: bool | None = None, jobs: int | None = None) -> str:
     sys.path.insert(0, CSRC)
     import gen_eri  # noqa: E402
     gen_eri.main(GEN)
-    digest = _headers_digest()
+    full, classes = _headers_digest(), _headers_digest(CLASS_HEADERS)
     srcs = _sources()
     # biggest sources first so the long compiles start early
     srcs.sort(key=lambda s: -os.path.getsize(s))
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, digest, incremental), srcs))
+        objs = list(ex.map(lambda s: _compile(s, _digest_for(s, full, classes), incremental), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -17,40 +17,53 @@
 // log2(nprim_a * nprim_d), f2 log10 of the unit's Schwarz row bound
 // (max_b Qn_ab * max_c Qn_cd), f3 log2(1 + candidate entries of the unit)
 // ---------------------------------------------------------------------------
-__global__ void fx_k_unit_features(const int* __restrict__ units, long nunits, const long* __restrict__ bc_off,
-                                   const long* __restrict__ cls_off, int seg, const int* __restrict__ nprim,
-                                   const double* __restrict__ qrow, float class_cost, float4* __restrict__ feat) {
-    const long u = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= nunits) return;
-    const int item = units[3 * u], a = units[3 * u + 1], d = units[3 * u + 2];
-    const long ne = cls_off ? (cls_off[(long)item * 10 + seg + 1] - cls_off[(long)item * 10 + seg])
-                            : (bc_off[item + 1] - bc_off[item]);
-    const double qb = qrow[a] * qrow[d];
-    float4 f;
-    f.x = class_cost;
-    f.y = log2f((float)(nprim[a] * nprim[d]));
-    f.z = (float)log10(qb > 1e-300 ? qb : 1e-300);
-    f.w = log2f(1.0f + (float)ne);
-    feat[u] = f;
+__global__ __launch_bounds__(256) void fx_k_unit_features(const int* __restrict__ units, const long* __restrict__ ulh,
+                                                          const long* __restrict__ bc_off,
+                                                          const long* __restrict__ cls_off, int seg,
+                                                          const int* __restrict__ nprim,
+                                                          const double* __restrict__ qrow, float class_cost,
+                                                          float4* __restrict__ feat, const long* __restrict__ feat_off) {
+    const long lo = ulh[0], n = ulh[1] - lo;
+    float4* out = feat + (feat_off ? *feat_off : 0);
+    for (long u = (long)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (long)gridDim.x * blockDim.x) {
+        const int item = units[3 * (lo + u)], a = units[3 * (lo + u) + 1], d = units[3 * (lo + u) + 2];
+        const long ne = cls_off ? (cls_off[(long)item * 10 + seg + 1] - cls_off[(long)item * 10 + seg])
+                                : (bc_off[item + 1] - bc_off[item]);
+        const double qb = qrow[a] * qrow[d];
+        float4 f;
+        f.x = class_cost;
+        f.y = log2f((float)(nprim[a] * nprim[d]));
+        f.z = (float)log10(qb > 1e-300 ? qb : 1e-300);
+        f.w = log2f(1.0f + (float)ne);
+        out[u] = f;
+    }
 }
 
-void fx_launch_unit_features(const int* units, long nunits, const long* bc_off, const long* cls_off, int seg,
-                             const int* nprim, const double* qrow, float class_cost, float4* feat, hipStream_t st) {
-    if (nunits > 0)
-        hipLaunchKernelGGL(fx_k_unit_features, dim3((nunits + 255) / 256), dim3(256), 0, st, units, nunits, bc_off,
-                           cls_off, seg, nprim, qrow, class_cost, feat);
+static long fx_cm_grid(long n, int block) {
+    long g = (n + block - 1) / block;
+    if (g > 8192) g = 8192;
+    return g < 1 ? 1 : g;
+}
+
+void fx_launch_unit_features(const int* units, const long* ulh, long n_max, const long* bc_off, const long* cls_off,
+                             int seg, const int* nprim, const double* qrow, float class_cost, float4* feat,
+                             const long* feat_off, hipStream_t st) {
+    hipLaunchKernelGGL(fx_k_unit_features, dim3(fx_cm_grid(n_max, 256)), dim3(256), 0, st, units, ulh, bc_off, cls_off,
+                       seg, nprim, qrow, class_cost, feat, feat_off);
 }
 
 // bound-only estimate: log2(class flops) + log2(nprim_a nprim_d) + log2(1 + entries)
-__global__ void fx_k_bound_cost(const float4* __restrict__ feat, long n, float* __restrict__ out) {
-    const long u = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n) return;
-    const float4 f = feat[u];
-    out[u] = f.x + f.y + f.w;
+__global__ __launch_bounds__(256) void fx_k_bound_cost(const float4* __restrict__ feat, const long* __restrict__ ulh,
+                                                       float* __restrict__ out) {
+    const long n = ulh[1] - ulh[0];
+    for (long u = (long)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (long)gridDim.x * blockDim.x) {
+        const float4 f = feat[u];
+        out[u] = f.x + f.y + f.w;
+    }
 }
 
-void fx_launch_bound_cost(const float4* feat, long n, float* out, hipStream_t st) {
-    if (n > 0) hipLaunchKernelGGL(fx_k_bound_cost, dim3((n + 255) / 256), dim3(256), 0, st, feat, n, out);
+void fx_launch_bound_cost(const float4* feat, const long* ulh, long n_max, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(fx_k_bound_cost, dim3(fx_cm_grid(n_max, 256)), dim3(256), 0, st, feat, ulh, out);
 }
 
 // max_b Qn[s][b] for every shell s
@@ -90,18 +103,24 @@ __device__ __forceinline__ void fx_mlp_forward(const float* __restrict__ W, cons
     y = o;
 }
 
-// prediction in target units: y * ystd + ymean
-__global__ void fx_k_mlp_predict(const float* __restrict__ W, const float* __restrict__ norm,
-                                 const float4* __restrict__ feat, long n, float* __restrict__ out) {
-    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    float h1[FX_MLP_H], h2[FX_MLP_H], y;
-    fx_mlp_forward(W, norm, feat[s], h1, h2, y);
-    out[s] = y * norm[9] + norm[8];
+// prediction in target units: y * ystd + ymean; n = ulh[1] - ulh[0] when
+// ulh is given, else n_host
+__global__ __launch_bounds__(128) void fx_k_mlp_predict(const float* __restrict__ W, const float* __restrict__ norm,
+                                                        const float4* __restrict__ feat, const long* __restrict__ ulh,
+                                                        long n_host, float* __restrict__ out) {
+    const long n = ulh ? ulh[1] - ulh[0] : n_host;
+    for (long s = (long)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (long)gridDim.x * blockDim.x) {
+        float h1[FX_MLP_H], h2[FX_MLP_H], y;
+        fx_mlp_forward(W, norm, feat[s], h1, h2, y);
+        out[s] = y * norm[9] + norm[8];
+    }
 }
 
-void fx_launch_mlp_predict(const float* W, const float* norm, const float4* feat, long n, float* out, hipStream_t st) {
-    if (n > 0) hipLaunchKernelGGL(fx_k_mlp_predict, dim3((n + 127) / 128), dim3(128), 0, st, W, norm, feat, n, out);
+void fx_launch_mlp_predict(const float* W, const float* norm, const float4* feat, const long* ulh, long n_max,
+                           float* out, hipStream_t st) {
+    if (n_max > 0)
+        hipLaunchKernelGGL(fx_k_mlp_predict, dim3(fx_cm_grid(n_max, 128)), dim3(128), 0, st, W, norm, feat, ulh,
+                           n_max, out);
 }
 
 // Per-sample forward and backward of the squared error on standardised
@@ -208,32 +227,79 @@ void fx_mlp_adam(float* W, const float* g, float* m, float* v, float lr, int t, 
 
 // ---------------------------------------------------------------------------
 // Binned launch order: key = bin of the predicted log-cost (heaviest first),
-// flags laid out bin-major, one exclusive scan gives every unit its position;
-// stable within a bin (units keep their traversal order).
+// a stable counting sort.  bin_count: per block of 256 units the count of
+// each bin (laid out bin-major, [bin][block]); one exclusive scan of the
+// counts; bin_scatter: position = scanned count of (bin, block) + rank of
+// the unit among the block's units of its bin (wave ballots).  Units keep
+// their list order inside a bin.  The unit count is read on the device.
 // ---------------------------------------------------------------------------
-__global__ void fx_k_bin_flags(const float* __restrict__ cost, long n, float top, float width, int nbins,
-                               int* __restrict__ flags, uint8_t* __restrict__ key) {
-    const long u = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n) return;
-    float b = (top - cost[u]) / width;
+#define FX_BIN_BLOCK 256
+
+__device__ __forceinline__ int fx_bin_of(float c, float top, float width, int nbins) {
+    const float b = (top - c) / width;
     int k = b < 0.f ? 0 : (b >= (float)(nbins - 1) ? nbins - 1 : (int)b);
-    if (!(cost[u] == cost[u])) k = nbins - 1;   // NaN last
-    key[u] = (uint8_t)k;
-    for (int q = 0; q < nbins; ++q) flags[(long)q * n + u] = (q == k);
+    if (!(c == c)) k = nbins - 1;   // NaN last
+    return k;
 }
 
-__global__ void fx_k_bin_scatter(const uint8_t* __restrict__ key, long n, const long* __restrict__ pos,
-                                 int* __restrict__ order) {
-    const long u = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n) return;
-    order[pos[(long)key[u] * n + u]] = (int)u;
+__global__ __launch_bounds__(FX_BIN_BLOCK) void fx_k_bin_count(const float* __restrict__ cost,
+                                                               const long* __restrict__ ulh, float top, float width,
+                                                               int nbins, long nblk, uint8_t* __restrict__ key,
+                                                               int* __restrict__ bcount) {
+    __shared__ int h[64];
+    const long n = ulh[1] - ulh[0];
+    for (long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        if (threadIdx.x < 64) h[threadIdx.x] = 0;
+        __syncthreads();
+        const long u = blk * FX_BIN_BLOCK + threadIdx.x;
+        if (u < n) {
+            const int k = fx_bin_of(cost[u], top, width, nbins);
+            key[u] = (uint8_t)k;
+            atomicAdd(&h[k], 1);   // an integer count: independent of the order of the additions
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nbins) bcount[(long)threadIdx.x * nblk + blk] = h[threadIdx.x];
+        __syncthreads();
+    }
 }
 
-void fx_launch_bin_order(const float* cost, long n, float top, float width, int nbins, int* flags, uint8_t* key,
-                         long* pos, long* partial, long* total, int* order, hipStream_t st,
+__global__ __launch_bounds__(FX_BIN_BLOCK) void fx_k_bin_scatter(const uint8_t* __restrict__ key,
+                                                                 const long* __restrict__ ulh, int nbins, long nblk,
+                                                                 const long* __restrict__ bpos,
+                                                                 int* __restrict__ order) {
+    __shared__ int wc[FX_BIN_BLOCK / 64][64];
+    const long n = ulh[1] - ulh[0];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const long u = blk * FX_BIN_BLOCK + threadIdx.x;
+        const int k = u < n ? (int)key[u] : -1;
+        int rank = 0;
+        for (int q = 0; q < nbins; ++q) {
+            const uint64_t m = __ballot(k == q);
+            if (k == q) rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            if (lane == 0) wc[w][q] = __popcll(m);
+        }
+        __syncthreads();
+        if (k >= 0) {
+            long p = bpos[(long)k * nblk + blk] + rank;
+            for (int v = 0; v < w; ++v) p += wc[v][k];
+            order[p] = (int)u;
+        }
+        __syncthreads();
+    }
+}
+
+long fx_bin_blocks(long n_max) { return (n_max + FX_BIN_BLOCK - 1) / FX_BIN_BLOCK; }
+
+void fx_launch_bin_order(const float* cost, const long* ulh, long n_max, float top, float width, int nbins,
+                         uint8_t* key, int* bcount, long* bpos, long* partial, long* total, int* order, hipStream_t st,
                          void (*scan)(const int*, long, long*, long*, long*, hipStream_t)) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(fx_k_bin_flags, dim3((n + 255) / 256), dim3(256), 0, st, cost, n, top, width, nbins, flags, key);
-    scan(flags, (long)nbins * n, pos, partial, total, st);
-    hipLaunchKernelGGL(fx_k_bin_scatter, dim3((n + 255) / 256), dim3(256), 0, st, key, n, pos, order);
+    const long nblk = fx_bin_blocks(n_max);
+    if (nblk <= 0) return;
+    const long g = nblk < 8192 ? nblk : 8192;
+    hipLaunchKernelGGL(fx_k_bin_count, dim3(g), dim3(FX_BIN_BLOCK), 0, st, cost, ulh, top, width, nbins, nblk, key,
+                       bcount);
+    scan(bcount, (long)nbins * nblk, bpos, partial, total, st);
+    hipLaunchKernelGGL(fx_k_bin_scatter, dim3(g), dim3(FX_BIN_BLOCK), 0, st, key, ulh, nbins, nblk, bpos, order);
 }

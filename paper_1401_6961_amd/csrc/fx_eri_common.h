@@ -143,8 +143,8 @@ __device__ __forceinline__ double fx_comp_factor(int l, int k) {
 // and evaluated 64 at a time, one per lane.  Each lane accumulates its
 // quartets' contributions to K_ad in FP64 registers; the 64 partial blocks
 // are reduced by a fixed butterfly, so the block is a deterministic function
-// of the unit, whatever order units are scheduled in.  The block is written
-// once to this class's (lb, lc, precision) slot: no atomics.
+// of the unit, whatever order units are scheduled in.  The block is added
+// once into the system's K accumulator: no atomics.
 // ---------------------------------------------------------------------------
 //
 // DUAL (mixed precision in one pass): each candidate is screened once and
@@ -164,9 +164,12 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
     constexpr int NA = fx_ncart(LA), ND = fx_ncart(LD);
     constexpr int NK = COOP ? 1 : NA * ND;   // K elements held per lane and density
     const int lane = fx_lane();
-    const int u = __builtin_amdgcn_readfirstlane(A.order ? A.order[slot_unit] : (int)slot_unit);
+    const long ulo = A.ulh[0];
+    const int ur = __builtin_amdgcn_readfirstlane(A.order ? A.order[slot_unit] : (int)slot_unit);
+    const long u = ulo + ur;
     const int sid = A.unit_sys ? __builtin_amdgcn_readfirstlane(A.unit_sys[u]) : -1;
     const FxSys Sy = sid >= 0 ? A.sys[sid] : A.one;
+    const int sym = __builtin_amdgcn_readfirstlane(Sy.cnt->sym);
     const uint64_t t_start = A.times ? wall_clock64() : 0;
     const int item = __builtin_amdgcn_readfirstlane(A.units[3 * u]);
     const int a = __builtin_amdgcn_readfirstlane(A.units[3 * u + 1]);
@@ -197,7 +200,8 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
     // 0: culled; 1: first queue; 2: second queue (DUAL, beta < thr)
     auto test = [&](int b, int c) -> int {
         const double beta = (Qa[b] * Qd[c]) * Sy.Pn[(long)b * S + c];
-        if (!(beta > tau)) return 0;
+        // leaf_screen BLOCK: every quartet of a surviving leaf task is computed
+        if (!(beta > tau) && !A.block) return 0;
         if (DUAL) return beta < thr ? 2 : 1;
         if (mode == FX_MODE_MIXED_HI) return beta < thr ? 0 : 1;
         if (mode == FX_MODE_MIXED_LO) return beta < thr ? 1 : 0;
@@ -345,13 +349,17 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
     }
 #pragma unroll
     for (int j = 0; j < NDENS; ++j) {
-        double* kslot = Sy.slots + j * Sy.slot_stride + (long)A.slot_index * Sy.n * Sy.n;
-        if (lane < NA * ND) kslot[rowbase + (long)(lane / ND) * Sy.n + (lane % ND)] = outv[j];
+        // K_ad += this class's block.  Class launches of one system run one
+        // after another on one stream and a launch has one unit per block, so
+        // each element has one writer at a time and the additions follow the
+        // launch order: no atomics, the same K for any schedule.
+        double* kout = Sy.acc[j];
+        if (lane < NA * ND) kout[rowbase + (long)(lane / ND) * Sy.n + (lane % ND)] += outv[j];
         // symmetric densities: K_da = K_ad^T, and unit (d, a) does not exist
-        if (Sy.sym && a != d && lane < NA * ND)
-            kslot[(long)(Bs.f0[d] + lane % ND) * Sy.n + Bs.f0[a] + lane / ND] = outv[j];
+        if (sym && a != d && lane < NA * ND)
+            kout[(long)(Bs.f0[d] + lane % ND) * Sy.n + Bs.f0[a] + lane / ND] += outv[j];
     }
-    if (A.times && lane == 0) A.times[u] = (float)(wall_clock64() - t_start);
+    if (A.times && lane == 0) A.times[ur] = (float)(wall_clock64() - t_start);
     auto count = [&](unsigned long long* ctr, long q, long npl) {
         long np = npl;
 #pragma unroll
@@ -359,7 +367,7 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
         if (lane == 0) {
             atomicAdd(ctr, (unsigned long long)q);
             atomicAdd(ctr + 1, (unsigned long long)np);
-            if (Sy.sym && a != d) atomicAdd(ctr + 2, (unsigned long long)q);
+            if (sym && a != d) atomicAdd(ctr + 2, (unsigned long long)q);
         }
     };
     if (A.counters) count(A.counters, nq, npq);
@@ -379,7 +387,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn, Fn2 f
     long blk = blockIdx.x;
     if (A.flags & FX_LAUNCH_XCD) blk = fx_xcd_remap(blk, gridDim.x);
     const long slot_unit = blk * WAVES + wave;
-    if (slot_unit >= A.nunits) return;
+    if (slot_unit >= __builtin_amdgcn_readfirstlane((int)(A.ulh[1] - A.ulh[0]))) return;
     fx_class_unit<LA, LB, LC, LD, COOP, WAVES, NDENS, DUAL>(A, fn, fn2, slot_unit, wave, queue, queue2);
 }
 
@@ -424,7 +432,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn, Fn2 f
         fx_class_body<la, lb, lc, ld, false, FX_CLASS_WAVES, 1, true>(A, f64, f32);                      \
     }
 #define FX_LAUNCH_DUAL(cls)                                                                             \
-    hipLaunchKernelGGL(fx_k_##cls##_mix, dim3((A.nunits + FX_CLASS_WAVES - 1) / FX_CLASS_WAVES),         \
+    hipLaunchKernelGGL(fx_k_##cls##_mix, dim3((A.nbound + FX_CLASS_WAVES - 1) / FX_CLASS_WAVES),         \
                        dim3(64 * FX_CLASS_WAVES), 0, st, A)
 
 // Cooperative variant: one quartet per wave, intermediates in LDS.
@@ -441,7 +449,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn, Fn2 f
 
 #define FX_LAUNCH_THREAD(cls, prec)                                                                     \
     do {                                                                                                 \
-        const dim3 g((A.nunits + FX_CLASS_WAVES - 1) / FX_CLASS_WAVES), b(64 * FX_CLASS_WAVES);          \
+        const dim3 g((A.nbound + FX_CLASS_WAVES - 1) / FX_CLASS_WAVES), b(64 * FX_CLASS_WAVES);          \
         if (A.ndens == 2)                                                                                \
             hipLaunchKernelGGL(fx_k_##cls##_##prec<2>, g, b, 0, st, A);                                  \
         else                                                                                             \
@@ -449,7 +457,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn, Fn2 f
     } while (0)
 #define FX_LAUNCH_COOP(cls, prec)                                                                       \
     hipLaunchKernelGGL(fx_kc_##cls##_##prec,                                                            \
-                       dim3((A.nunits + FX_COOP_WAVES - 1) / FX_COOP_WAVES),           \
+                       dim3((A.nbound + FX_COOP_WAVES - 1) / FX_COOP_WAVES),           \
                        dim3(64 * FX_COOP_WAVES), 0, st, A)
 
 // Both variants; `variant` 0 = thread, 1 = cooperative.

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -22,6 +23,7 @@
 #include <vector>
 
 #include "../../include/fx.h"
+#include "fx_host.h"
 #include "eri_flops.h"
 #include "eri_table.h"
 #include "fx_costmodel.h"
@@ -29,126 +31,13 @@
 #include "fx_kernels.h"
 
 // ---------------------------------------------------------------------------
-// errors
+// process-wide state declared in fx_host.h
 // ---------------------------------------------------------------------------
-static thread_local std::string g_last_error;
-
-struct FxError {
-    fx_status st;
-    std::string msg;
-};
-
-[[noreturn]] static void fx_fail(fx_status st, const std::string& msg) { throw FxError{st, msg}; }
-
-#define FX_HIP(call)                                                                                   \
-    do {                                                                                               \
-        hipError_t e_ = (call);                                                                        \
-        if (e_ != hipSuccess) fx_fail(FX_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-static fx_status fx_guard_status(const FxError& e) {
-    g_last_error = e.msg;
-    return e.st;
-}
-
-template <typename F>
-static fx_status fx_guard(F&& f) {
-    try {
-        f();
-        g_last_error.clear();
-        return FX_OK;
-    } catch (const FxError& e) {
-        return fx_guard_status(e);
-    } catch (const std::bad_alloc&) {
-        g_last_error = "host allocation failed";
-        return FX_ERR_OOM;
-    } catch (...) {
-        g_last_error = "internal error";
-        return FX_ERR_INTERNAL;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// device memory
-// ---------------------------------------------------------------------------
-static fx_alloc_fn g_alloc = nullptr;
-static fx_free_fn g_free = nullptr;
-static void* g_alloc_ctx = nullptr;
-
-static void* fx_dalloc(size_t bytes, hipStream_t st, bool persistent = false) {
-    if (bytes == 0) bytes = 8;
-    void* p = nullptr;
-    if (persistent) {
-        // memory owned by a tree handle outlives the caller's stream
-        if (hipMalloc(&p, bytes) != hipSuccess || !p) {
-            (void)hipGetLastError();
-            fx_fail(FX_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-        }
-        return p;
-    }
-    if (g_alloc) {
-        p = g_alloc(bytes, (void*)st, g_alloc_ctx);
-        if (!p) fx_fail(FX_ERR_OOM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes");
-        return p;
-    }
-    hipError_t e = hipMallocAsync(&p, bytes, st);
-    if (e != hipSuccess || !p) {
-        (void)hipGetLastError();
-        fx_fail(FX_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-    }
-    return p;
-}
-
-static void fx_dfree(void* p, hipStream_t st, bool persistent = false) {
-    if (!p) return;
-    if (persistent) {
-        (void)hipFree(p);
-        return;
-    }
-    if (g_free) g_free(p, (void*)st, g_alloc_ctx);
-    else (void)hipFreeAsync(p, st);
-}
-
-// RAII set of device allocations tied to a stream
-struct DevArena {
-    hipStream_t st;
-    bool persistent;
-    std::vector<void*> ptrs;
-    explicit DevArena(hipStream_t s, bool pers = false) : st(s), persistent(pers) {}
-    template <typename T>
-    T* get(size_t count) {
-        T* p = (T*)fx_dalloc(sizeof(T) * count, st, persistent);
-        ptrs.push_back(p);
-        return p;
-    }
-    void release(void* p) {
-        auto it = std::find(ptrs.begin(), ptrs.end(), p);
-        if (it != ptrs.end()) {
-            fx_dfree(p, st, persistent);
-            ptrs.erase(it);
-        }
-    }
-    ~DevArena() {
-        for (void* p : ptrs) fx_dfree(p, st, persistent);
-    }
-};
-
-template <typename T>
-static T* upload(DevArena& A, const std::vector<T>& v) {
-    T* d = A.get<T>(v.size());
-    if (!v.empty()) FX_HIP(hipMemcpyAsync(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, A.st));
-    return d;
-}
-
-template <typename T>
-static T read1(const T* dptr, hipStream_t st) {
-    T v;
-    FX_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, st));
-    FX_HIP(hipStreamSynchronize(st));
-    return v;
-}
-
-static int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+thread_local std::string g_last_error;
+fx_alloc_fn g_alloc = nullptr;
+fx_free_fn g_free = nullptr;
+void* g_alloc_ctx = nullptr;
+thread_local fx_task_timings* g_recording = nullptr;
 
 // ---------------------------------------------------------------------------
 // Boys table F_j(T_i), T_i = i/32: the convergent series
@@ -204,18 +93,6 @@ extern "C" uint64_t fx_hilbert_key3(uint32_t x, uint32_t y, uint32_t z, int32_t 
         for (int i = 0; i < 3; ++i) key = (key << 1) | ((X[i] >> b) & 1u);
     return key;
 }
-
-// ---------------------------------------------------------------------------
-// host plan: ordering + ragged bisection
-// ---------------------------------------------------------------------------
-struct Level {
-    std::vector<int> sL, sR, ch0, nch;  // nodes of this level; ch0/nch index level+1
-};
-
-struct Plan {
-    std::vector<int> order;   // tree position -> caller shell index
-    std::vector<Level> levels;
-};
 
 static void validate_shells(const fx_shells* s) {
     if (!s) fx_fail(FX_ERR_INVALID_ARG, "shells is NULL");
@@ -308,58 +185,18 @@ static Plan make_plan(const fx_shells* s, const fx_tree_opts* opts) {
     return P;
 }
 
-// ---------------------------------------------------------------------------
-// the tree handle
-// ---------------------------------------------------------------------------
-struct fx_tree {
-    int S = 0, n = 0, lmax = 0;
-    std::vector<int> order;          // tree position -> caller shell
-    std::vector<int> l, nprim;       // tree order
-    std::vector<int> f0;             // tree order, caller function offset
-    std::vector<Level> levels;
-    std::vector<int> leaf_lofs;      // host copy
-    bool single_shell_leaves = false;
-    hipStream_t build_stream = nullptr;
-    DevArena* arena = nullptr;
-    FxDevBasis basis{};
-    double* boys = nullptr;
-    std::vector<int*> d_sL, d_sR, d_ch0, d_nch;
-    std::vector<double*> d_Qsq;      // per level (nk x nk)
-    double* qrow = nullptr;          // max_b Qn[s][b]
-    float mean_np[3] = {1, 1, 1};    // mean primitive count of the shells of each l
-    ~fx_tree() {
-        if (arena) (void)hipDeviceSynchronize();
-        delete arena;
-    }
-};
-
-struct fx_costmodel {
-    std::vector<float> W, norm;    // FX_MLP_NPARAM, FX_MLP_NNORM
-    float* dW = nullptr;
-    float* dnorm = nullptr;
-    ~fx_costmodel() {
-        if (dW) (void)hipFree(dW);
-        if (dnorm) (void)hipFree(dnorm);
-    }
-    void upload() {
-        if (!dW) {
-            if (hipMalloc(&dW, sizeof(float) * FX_MLP_NPARAM) != hipSuccess ||
-                hipMalloc(&dnorm, sizeof(float) * FX_MLP_NNORM) != hipSuccess)
-                fx_fail(FX_ERR_OOM, "cost model allocation failed");
-        }
-        FX_HIP(hipMemcpy(dW, W.data(), sizeof(float) * FX_MLP_NPARAM, hipMemcpyHostToDevice));
-        FX_HIP(hipMemcpy(dnorm, norm.data(), sizeof(float) * FX_MLP_NNORM, hipMemcpyHostToDevice));
-    }
-};
-
-struct fx_task_timings {
-    std::vector<float> feat;    // 4 per sample
-    std::vector<float> log2ns;  // measured unit time
-    std::vector<int> cls;       // cls * 2 + fp32
-};
+static std::atomic<uint64_t> g_tree_ids{1};
 
 static void build_tree(const fx_shells* s, const fx_tree_opts* opts, hipStream_t st, fx_tree* T) {
     validate_shells(s);
+    T->id = g_tree_ids.fetch_add(1);
+    if (hipHostMalloc((void**)&T->usage, sizeof(FxDevRun), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        T->usage = nullptr;
+        fx_fail(FX_ERR_OOM, "pinned host allocation failed");
+    }
+    std::memset(T->usage, 0, sizeof(FxDevRun));
+    FX_HIP(hipEventCreateWithFlags(&T->usage_ev, hipEventDisableTiming));
     Plan P = make_plan(s, opts);
     const int S = s->nshell;
     T->S = S;
@@ -465,11 +302,16 @@ static void build_tree(const fx_shells* s, const fx_tree_opts* opts, hipStream_t
         B.ntprim = Nt;
         B.pp = pp;
     }
+    std::vector<int> tfp(S + 1, 0);
+    for (int t = 0; t < S; ++t) tfp[t + 1] = tfp[t] + ncart(l[t]);
     for (const Level& L : P.levels) {
         T->d_sL.push_back(upload(A, L.sL));
         T->d_sR.push_back(upload(A, L.sR));
         T->d_ch0.push_back(upload(A, L.ch0));
         T->d_nch.push_back(upload(A, L.nch));
+        std::vector<int> nf(L.sL.size());
+        for (size_t i = 0; i < nf.size(); ++i) nf[i] = tfp[L.sR[i]] - tfp[L.sL[i]];
+        T->d_nf.push_back(upload(A, nf));
     }
     // Schwarz norms of all shell pairs
     double* Qn = A.get<double>((size_t)S * S);
@@ -516,8 +358,8 @@ static void build_tree(const fx_shells* s, const fx_tree_opts* opts, hipStream_t
 // quartet) and launch flags (FX_LAUNCH_*); thread form, no flags by default,
 // the autotuner may switch
 // ---------------------------------------------------------------------------
-static int g_variant[81][2];
-static int g_flags[81][2];
+int g_variant[81][2];
+int g_flags[81][2];
 static bool g_variant_init = [] {
     for (int c = 0; c < 81; ++c)
         for (int p = 0; p < 2; ++p) {
@@ -526,626 +368,6 @@ static bool g_variant_init = [] {
         }
     return true;
 }();
-
-// ---------------------------------------------------------------------------
-// exchange
-// ---------------------------------------------------------------------------
-struct Frontier {
-    int2* ad;
-    long* bc_off;      // absolute offsets into bc for ad[0..nad]
-    int2* bc;
-    int* parent;
-    int nad;
-    long e_begin, e_count;
-    int p_base;
-};
-
-// one system of a call: tree, density, output and its per-call arrays
-struct SysCtx {
-    const fx_tree* T = nullptr;
-    const double* P[FX_MAX_DENS] = {nullptr, nullptr};
-    double* K[FX_MAX_DENS] = {nullptr, nullptr};
-    double* Pn = nullptr;
-    std::vector<double*> Psq;
-    double* slots = nullptr;
-    int sym = 0;                    // symmetric density: only K blocks a <= d are built
-};
-
-// a leaf-level traversal chunk, ready for the class launches
-struct LeafSeg {
-    std::unique_ptr<DevArena> arena;
-    FxSys sys{};
-    const fx_tree* T = nullptr;
-    int* units = nullptr;
-    long bounds[10] = {0};
-    long nitems = 0;
-};
-
-struct ExCtx {
-    double tau;
-    hipStream_t st;
-    int precision;
-    double thr;
-    int schedule;
-    const fx_costmodel* cm;
-    long cap;
-    int L;                          // slot layout: (highest l + 1)^2 (x2 in mixed mode)
-    int nslot;
-    int ndens = 1;                  // densities per system, contracted with the same integrals
-    bool collect = false;           // batched: keep leaf segments for one launch per class
-    bool use_graph = false;
-    std::vector<std::unique_ptr<LeafSeg>> segs;
-    unsigned long long* counters;   // [81][2][2]: quartets, primitive quartets per class and precision
-    fx_stats* stats;
-    long* scan_partial;
-    long scan_partial_cap;
-    long* scan_total;
-    double seconds_eri = 0;
-    int profile = 0;
-    fx_task_timings* rec = nullptr;   // timing-probe collection
-    double tick_ns = 10.0;            // wall-clock tick
-    struct Timed {
-        int idx;
-        hipEvent_t a, b;
-    };
-    std::vector<Timed> timed;
-};
-
-static thread_local fx_task_timings* g_recording = nullptr;
-
-static int slot_index(const ExCtx& c, int lb, int lc, int prec32) {
-    return (lb * c.L + lc) * (c.precision == FX_PREC_MIXED ? 2 : 1) + prec32;
-}
-
-static long* scan_partial(ExCtx& c, DevArena& A, long n) {
-    const long need = fx_scan_tiles(n);
-    if (need > c.scan_partial_cap) return A.get<long>(need);
-    return c.scan_partial;
-}
-
-// Units (K blocks) of a leaf chunk and, for single-shell leaves, its entries
-// grouped by density-side class.  In collect mode the chunk's entries are
-// copied so that the segment outlives the traversal.
-static std::unique_ptr<LeafSeg> prepare_seg(ExCtx& c, SysCtx& sc, const Frontier& f) {
-    const fx_tree* T = sc.T;
-    hipStream_t st = c.st;
-    auto seg = std::make_unique<LeafSeg>();
-    seg->arena = std::make_unique<DevArena>(st);
-    DevArena& A = *seg->arena;
-    seg->T = T;
-    const long nitems = f.nad;
-    seg->nitems = nitems;
-    if (f.e_begin != 0) fx_fail(FX_ERR_INTERNAL, "leaf frontier does not start at entry 0");
-    if (c.stats) c.stats->leaf_items += nitems;
-    int* cnt = A.get<int>(9 * nitems);
-    long* upos = A.get<long>(9 * nitems + 1);
-    fx_launch_unit_count(f.ad, nitems, T->basis.leaf_lofs, T->basis.leaf_lsh, sc.sym, cnt, st);
-    fx_scan_i32(cnt, 9 * nitems, upos, scan_partial(c, A, 9 * nitems), c.scan_total, st);
-    for (int k = 0; k < 9; ++k)
-        FX_HIP(hipMemcpyAsync(&seg->bounds[k], upos + (long)k * nitems, sizeof(long), hipMemcpyDeviceToHost, st));
-    FX_HIP(hipMemcpyAsync(&seg->bounds[9], upos + 9 * nitems, sizeof(long), hipMemcpyDeviceToHost, st));
-    FX_HIP(hipStreamSynchronize(st));
-    const long nunits = seg->bounds[9];
-    if (c.stats) c.stats->units += nunits;
-    seg->units = A.get<int>(3 * std::max(1L, nunits));
-    fx_launch_unit_write(f.ad, nitems, 0, T->basis.leaf_lofs, T->basis.leaf_lsh, sc.sym, upos, seg->units, st);
-    A.release(cnt);
-    A.release(upos);
-    FxSys& Y = seg->sys;
-    Y.basis = T->basis;
-    for (int j = 0; j < FX_MAX_DENS; ++j) Y.P[j] = sc.P[j < c.ndens ? j : 0];
-    Y.n = T->n;
-    Y.Pn = sc.Pn;
-    Y.bc_off = f.bc_off;
-    Y.bc = f.bc;
-    Y.cls_off = nullptr;
-    Y.slots = sc.slots;
-    Y.slot_stride = (long)c.nslot * T->n * T->n;
-    Y.sym = sc.sym;
-    const long ne = std::max(1L, f.e_count);
-    if (T->single_shell_leaves) {
-        int2* sorted = A.get<int2>(ne);
-        long* cls_off = A.get<long>(10 * nitems);
-        fx_launch_class_sort(f.bc_off, f.bc, nitems, T->basis.l, sorted, cls_off, st);
-        Y.bc = sorted;
-        Y.cls_off = cls_off;
-    }
-    if (c.collect) {
-        long* off = A.get<long>(nitems + 1);
-        FX_HIP(hipMemcpyAsync(off, f.bc_off, sizeof(long) * (nitems + 1), hipMemcpyDeviceToDevice, st));
-        Y.bc_off = off;
-        if (!T->single_shell_leaves) {
-            int2* bc = A.get<int2>(ne);
-            FX_HIP(hipMemcpyAsync(bc, f.bc, sizeof(int2) * f.e_count, hipMemcpyDeviceToDevice, st));
-            Y.bc = bc;
-        }
-    }
-    FX_HIP(hipGetLastError());
-    return seg;
-}
-
-// One launch per class and precision over the units of all segments.
-static void run_classes(ExCtx& c, const std::vector<LeafSeg*>& segs) {
-    hipStream_t st = c.st;
-    if (segs.empty()) return;
-    DevArena A(st);
-    const bool multi = segs.size() > 1;
-    int lmax = 0;
-    for (auto* g : segs) lmax = std::max(lmax, g->T->lmax);
-    // per (la, ld): merged unit lists
-    long total[9] = {0}, maxlist = 0;
-    for (int k = 0; k < 9; ++k) {
-        for (auto* g : segs) total[k] += g->bounds[k + 1] - g->bounds[k];
-        maxlist = std::max(maxlist, total[k]);
-    }
-    if (maxlist == 0) return;
-    int* munits[9] = {nullptr};
-    int* msys[9] = {nullptr};
-    FxSys* dsys = nullptr;
-    if (multi) {
-        std::vector<FxSys> hs;
-        for (auto* g : segs) hs.push_back(g->sys);
-        dsys = upload(A, hs);
-        for (int k = 0; k < 9; ++k) {
-            if (!total[k]) continue;
-            munits[k] = A.get<int>(3 * total[k]);
-            msys[k] = A.get<int>(total[k]);
-            long o = 0;
-            for (size_t j = 0; j < segs.size(); ++j) {
-                const long n = segs[j]->bounds[k + 1] - segs[j]->bounds[k];
-                if (!n) continue;
-                FX_HIP(hipMemcpyAsync(munits[k] + 3 * o, segs[j]->units + 3 * segs[j]->bounds[k], sizeof(int) * 3 * n,
-                                      hipMemcpyDeviceToDevice, st));
-                fx_launch_fill_i32(msys[k] + o, n, (int)j, st);
-                o += n;
-            }
-        }
-    }
-    const bool sched = c.schedule != FX_SCHED_NONE;
-    const bool use_mlp = c.schedule == FX_SCHED_MLP && c.cm;
-    const int nbins = 32;
-    const bool graph = c.use_graph && !c.profile && !c.rec;
-    // scheduling buffers (features, predicted costs, bins, launch order)
-    struct Sched {
-        float4* feat = nullptr;
-        float* cost = nullptr;
-        int* flags = nullptr;
-        uint8_t* key = nullptr;
-        long* bpos = nullptr;
-        int* order = nullptr;
-        long* bpartial = nullptr;
-        long* total = nullptr;
-    } ln;
-    float* times = nullptr;
-    if (sched || c.rec) {
-        ln.feat = A.get<float4>(maxlist);
-        ln.cost = A.get<float>(maxlist);
-    }
-    if (sched) {
-        ln.flags = A.get<int>((size_t)nbins * maxlist);
-        ln.key = A.get<uint8_t>(maxlist);
-        ln.bpos = A.get<long>((size_t)nbins * maxlist + 1);
-        ln.order = A.get<int>(maxlist);
-        ln.bpartial = A.get<long>(fx_scan_tiles((long)nbins * maxlist));
-        ln.total = A.get<long>(1);
-    }
-    if (c.rec) times = A.get<float>(maxlist);
-    hipGraph_t gr = nullptr;
-    // Capture on a library-owned stream (the caller's may be the legacy default
-    // stream, which cannot be captured); the graph is then launched on `st`.
-    hipStream_t launch_st = st;
-    struct CapStream {
-        hipStream_t s = nullptr;
-        ~CapStream() {
-            if (s) (void)hipStreamDestroy(s);
-        }
-    } cap;
-    if (graph) {
-        FX_HIP(hipStreamCreateWithFlags(&cap.s, hipStreamNonBlocking));
-        FX_HIP(hipStreamBeginCapture(cap.s, hipStreamCaptureModeThreadLocal));
-        st = cap.s;
-    }
-    std::vector<float> hfeat, htime;
-    FxClassArgs args{};
-    args.boys = segs[0]->T->boys;
-    args.ndens = c.ndens;
-    args.tau = c.tau;
-    args.thr = c.thr;
-    const float* mean_np = segs[0]->T->mean_np;
-    for (int la = 0; la <= lmax; ++la)
-        for (int ld = 0; ld <= lmax; ++ld) {
-            const int k2 = la * 3 + ld;
-            if (!total[k2]) continue;
-            args.nunits = total[k2];
-            if (multi) {
-                args.units = munits[k2];
-                args.unit_sys = msys[k2];
-                args.sys = dsys;
-            } else {
-                args.units = segs[0]->units + 3 * segs[0]->bounds[k2];
-                args.unit_sys = nullptr;
-                args.sys = nullptr;
-                args.one = segs[0]->sys;
-            }
-            for (int lb = 0; lb <= lmax; ++lb)
-                for (int lc = 0; lc <= lmax; ++lc) {
-                    const int cls = ((la * 3 + lb) * 3 + lc) * 3 + ld;
-                    const int nprec = c.precision == FX_PREC_MIXED ? 2 : 1;
-                    const float class_cost =
-                        std::log2((float)fx_class_vrr_flops[cls] * mean_np[lb] * mean_np[lc] +
-                                  (float)fx_class_hrr_flops[cls] + 1.f);
-                    args.order = nullptr;
-                    args.times = nullptr;
-                    hipStream_t ls = st;
-                    if (ln.feat) {
-                        long o = 0;
-                        for (auto* g : segs) {
-                            const long n = g->bounds[k2 + 1] - g->bounds[k2];
-                            if (n)
-                                fx_launch_unit_features(g->units + 3 * g->bounds[k2], n, g->sys.bc_off, g->sys.cls_off,
-                                                        lb * 3 + lc, g->T->basis.nprim, g->T->qrow, class_cost,
-                                                        ln.feat + o, ls);
-                            o += n;
-                        }
-                    }
-                    if (sched) {
-                        // predicted log2 cost per unit: the learned model, or the
-                        // bound-only estimate log2(class flops * nprim_a nprim_d * entries)
-                        if (use_mlp)
-                            fx_launch_mlp_predict(c.cm->dW, c.cm->dnorm, ln.feat, args.nunits, ln.cost, ls);
-                        else
-                            fx_launch_bound_cost(ln.feat, args.nunits, ln.cost, ls);
-                        fx_launch_bin_order(ln.cost, args.nunits, use_mlp ? 40.f : 48.f, 1.0f, nbins, ln.flags,
-                                            ln.key, ln.bpos, ln.bpartial, ln.total, ln.order, ls, fx_scan_i32);
-                        args.order = ln.order;
-                    }
-                    // mixed precision in one pass (variant 2 on the FP64 entry, one density)
-                    const bool dual = nprec == 2 && c.ndens == 1 && g_variant[cls][0] == 2;
-                    for (int pr = 0; pr < (dual ? 1 : nprec); ++pr) {
-                        if (c.rec) args.times = times;
-                        args.mode = dual ? FX_MODE_DUAL
-                                         : c.precision == FX_PREC_MIXED ? (pr ? FX_MODE_MIXED_LO : FX_MODE_MIXED_HI)
-                                                                        : FX_MODE_ALL;
-                        args.slot_index = slot_index(c, lb, lc, pr);
-                        args.counters = c.counters + (cls * 2 + pr) * 3;
-                        args.counters2 = dual ? c.counters + (cls * 2 + 1) * 3 : nullptr;
-                        args.flags = g_flags[cls][pr];
-                        if (c.profile) {
-                            // events on the stream the kernel is launched on
-                            ExCtx::Timed t{cls * 2 + pr, nullptr, nullptr};
-                            FX_HIP(hipEventCreate(&t.a));
-                            FX_HIP(hipEventCreate(&t.b));
-                            FX_HIP(hipEventRecord(t.a, ls));
-                            fx_class_table[cls](pr, g_variant[cls][pr], args, ls);
-                            FX_HIP(hipEventRecord(t.b, ls));
-                            c.timed.push_back(t);
-                        } else {
-                            fx_class_table[cls](pr, g_variant[cls][pr], args, ls);
-                        }
-                        if (c.rec) {
-                            const long n = args.nunits;
-                            hfeat.resize(4 * n);
-                            htime.resize(n);
-                            FX_HIP(hipMemcpyAsync(hfeat.data(), ln.feat, sizeof(float4) * n, hipMemcpyDeviceToHost, ls));
-                            FX_HIP(hipMemcpyAsync(htime.data(), times, sizeof(float) * n, hipMemcpyDeviceToHost, ls));
-                            FX_HIP(hipStreamSynchronize(ls));
-                            for (long u = 0; u < n; ++u) {
-                                for (int q = 0; q < 4; ++q) c.rec->feat.push_back(hfeat[4 * u + q]);
-                                c.rec->log2ns.push_back(std::log2(std::max(1.0, (double)htime[u] * c.tick_ns)));
-                                c.rec->cls.push_back(cls * 2 + pr);
-                            }
-                        }
-                    }
-                }
-        }
-    if (graph) {
-        FX_HIP(hipStreamEndCapture(cap.s, &gr));
-        st = launch_st;
-        hipGraphExec_t ge = nullptr;
-        hipError_t e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
-        if (e == hipSuccess) e = hipGraphLaunch(ge, st);
-        if (ge) (void)hipGraphExecDestroy(ge);
-        (void)hipGraphDestroy(gr);
-        if (e != hipSuccess) fx_fail(FX_ERR_HIP, std::string("class-launch graph: ") + hipGetErrorString(e));
-        if (c.stats) c.stats->graph_nodes += 1;
-    }
-    FX_HIP(hipGetLastError());
-    FX_HIP(hipStreamSynchronize(st));
-}
-
-static void leaf_work(ExCtx& c, SysCtx& sc, const Frontier& f) {
-    if (f.nad == 0) return;
-    auto seg = prepare_seg(c, sc, f);
-    if (c.collect) {
-        c.segs.push_back(std::move(seg));
-        return;
-    }
-    run_classes(c, {seg.get()});
-}
-
-static void traverse(ExCtx& c, SysCtx& sc, int k, const Frontier& f) {
-    const fx_tree* T = sc.T;
-    hipStream_t st = c.st;
-    const int nl = (int)T->levels.size();
-    if (c.stats) c.stats->frontier[k] += f.e_count;
-    if (k == nl - 1) {
-        auto t0 = std::chrono::steady_clock::now();
-        leaf_work(c, sc, f);
-        c.seconds_eri += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        return;
-    }
-    if (f.e_count == 0) return;
-    DevArena A(st);
-    FxLevelArgs L{};
-    L.ad = f.ad;
-    L.bc_off = f.bc_off;
-    L.bc = f.bc;
-    L.bc_parent = f.parent;
-    L.e_begin = f.e_begin;
-    L.e_count = f.e_count;
-    L.p_base = f.p_base;
-    L.nad = f.nad;
-    L.ch0 = T->d_ch0[k];
-    L.nch = T->d_nch[k];
-    L.Qsq = T->d_Qsq[k + 1];
-    L.Psq = sc.Psq[k + 1];
-    L.nk1 = (int)T->levels[k + 1].sL.size();
-    L.tau2 = c.tau * c.tau;
-    L.sym = sc.sym;
-    const long nm = 4 * f.e_count;
-    uint8_t* mask = A.get<uint8_t>(nm);
-    long* pos = A.get<long>(nm + 1);
-    fx_launch_expand_mask(L, mask, st);
-    fx_scan_popc_u8(mask, nm, pos, scan_partial(c, A, nm), c.scan_total, st);
-    FX_HIP(hipGetLastError());
-    const long total = read1(c.scan_total, st);
-    if (total > c.cap && f.nad > 1) {
-        // chunk: split this level's ADs in two halves and traverse each
-        A.release(mask);
-        A.release(pos);
-        const int h = f.nad / 2;
-        const long mid = read1(f.bc_off + h, st);
-        Frontier f1 = f, f2 = f;
-        f1.nad = h;
-        f1.e_count = mid - f.e_begin;
-        f2.ad = f.ad + h;
-        f2.bc_off = f.bc_off + h;
-        f2.nad = f.nad - h;
-        f2.e_begin = mid;
-        f2.e_count = f.e_begin + f.e_count - mid;
-        f2.p_base = f.p_base + h;
-        if (c.stats) {
-            c.stats->chunks += 1;
-            c.stats->frontier[k] -= f.e_count;   // re-counted by the halves
-        }
-        traverse(c, sc, k, f1);
-        traverse(c, sc, k, f2);
-        return;
-    }
-    if (total > (1L << 31) - 1) fx_fail(FX_ERR_OOM, "a single K block pair exceeds the frontier capacity");
-    int* flag = A.get<int>(4L * f.nad);
-    long* adpos = A.get<long>(4L * f.nad + 1);
-    fx_launch_expand_adflag(L, pos, flag, st);
-    fx_scan_i32(flag, 4L * f.nad, adpos, scan_partial(c, A, 4L * f.nad), c.scan_total, st);
-    const long nads = read1(c.scan_total, st);
-    DevArena N(st);
-    Frontier g{};
-    g.ad = N.get<int2>(std::max(1L, nads));
-    g.bc_off = N.get<long>(nads + 1);
-    g.bc = N.get<int2>(std::max(1L, total));
-    const bool last = (k + 1 == nl - 1);   // the leaf level needs no parent links
-    g.parent = last ? nullptr : N.get<int>(std::max(1L, total));
-    g.nad = (int)nads;
-    g.e_begin = 0;
-    g.e_count = total;
-    g.p_base = 0;
-    fx_launch_expand_adwrite(L, pos, flag, adpos, g.ad, g.bc_off, total, nads, st);
-    fx_launch_expand_write(L, mask, pos, adpos, g.bc, g.parent, st);
-    FX_HIP(hipGetLastError());
-    A.release(mask);
-    A.release(pos);
-    A.release(flag);
-    A.release(adpos);
-    traverse(c, sc, k + 1, g);
-}
-
-static void validate_exchange(const fx_tree* T, const double* P, double tau, const double* K) {
-    if (!T) fx_fail(FX_ERR_INVALID_ARG, "tree is NULL");
-    if (!P || !K) fx_fail(FX_ERR_INVALID_ARG, "P and K must be device pointers");
-    if (P == K) fx_fail(FX_ERR_INVALID_ARG, "P must not alias K");
-    if (!(tau >= 0.0) || !std::isfinite(tau)) fx_fail(FX_ERR_INVALID_ARG, "tau must be finite and >= 0");
-    if (((uintptr_t)P & 7) || ((uintptr_t)K & 7)) fx_fail(FX_ERR_INVALID_ARG, "P and K must be 8-byte aligned");
-}
-
-static fx_exchange_opts checked_opts(const fx_exchange_opts* opts) {
-    fx_exchange_opts o{};
-    o.precision = FX_PREC_FP64;
-    o.fp32_threshold = 1e-5;
-    o.schedule = FX_SCHED_BOUND;
-    o.alpha = 1.0;
-    o.beta = 0.0;
-    if (opts) o = *opts;
-    if (o.precision != FX_PREC_FP64 && o.precision != FX_PREC_MIXED) fx_fail(FX_ERR_INVALID_ARG, "bad precision");
-    if (o.schedule < 0 || o.schedule > 2) fx_fail(FX_ERR_INVALID_ARG, "bad schedule");
-    if (!std::isfinite(o.alpha) || !std::isfinite(o.beta)) fx_fail(FX_ERR_INVALID_ARG, "alpha/beta not finite");
-    if (o.precision == FX_PREC_MIXED && !(o.fp32_threshold >= 0.0)) fx_fail(FX_ERR_INVALID_ARG, "bad fp32_threshold");
-    if (o.symmetry != FX_SYM_AUTO && o.symmetry != FX_SYM_OFF) fx_fail(FX_ERR_INVALID_ARG, "bad symmetry");
-    return o;
-}
-
-// Exchange of one or several systems.  Several systems are traversed one
-// after another, their leaf segments kept, and every class kernel is then
-// launched once over the units of all systems.
-// Ps, Ks: count * ndens device pointers, system-major.
-static void exchange_many(const fx_tree* const* trees, const double* const* Ps, double* const* Ks, int count,
-                          int ndens, double tau, const fx_exchange_opts* opts, fx_stats* stats, hipStream_t st) {
-    auto t0 = std::chrono::steady_clock::now();
-    if (ndens < 1 || ndens > FX_MAX_DENS)
-        fx_fail(FX_ERR_UNSUPPORTED, "ndens must be 1.." + std::to_string(FX_MAX_DENS));
-    for (int i = 0; i < count; ++i)
-        for (int j = 0; j < ndens; ++j) {
-            validate_exchange(trees[i], Ps[i * ndens + j], tau, Ks[i * ndens + j]);
-            for (int k = 0; k < ndens; ++k) {
-                if (Ps[i * ndens + j] == Ks[i * ndens + k]) fx_fail(FX_ERR_INVALID_ARG, "a density aliases a K");
-                if (k != j && Ks[i * ndens + j] == Ks[i * ndens + k]) fx_fail(FX_ERR_INVALID_ARG, "two K alias");
-            }
-        }
-    const fx_exchange_opts o = checked_opts(opts);
-    if (stats) std::memset(stats, 0, sizeof(*stats));
-    if (count == 0) return;
-    DevArena A(st);
-    ExCtx c{};
-    c.tau = tau;
-    c.st = st;
-    c.precision = o.precision;
-    c.thr = o.fp32_threshold;
-    c.schedule = o.schedule;
-    c.cm = o.costmodel;
-    c.cap = o.max_frontier_entries > 0 ? o.max_frontier_entries : (1L << 30);
-    c.stats = stats;
-    c.profile = o.profile;
-    c.ndens = ndens;
-    c.collect = count > 1;
-    c.use_graph = o.use_graph != 0;
-    c.rec = g_recording;
-    if (c.rec) {
-        int dev = 0, khz = 0;
-        FX_HIP(hipGetDevice(&dev));
-        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
-            c.tick_ns = 1e6 / (double)khz;
-    }
-    if (o.schedule == FX_SCHED_MLP && !o.costmodel) c.schedule = FX_SCHED_BOUND;
-    int lmax = 0;
-    for (int i = 0; i < count; ++i) lmax = std::max(lmax, trees[i]->lmax);
-    c.L = lmax + 1;
-    c.nslot = c.L * c.L * (o.precision == FX_PREC_MIXED ? 2 : 1);
-    c.counters = A.get<unsigned long long>(81 * 2 * 3);
-    FX_HIP(hipMemsetAsync(c.counters, 0, sizeof(unsigned long long) * 81 * 2 * 3, st));
-    c.scan_partial_cap = 1 << 16;
-    c.scan_partial = A.get<long>(c.scan_partial_cap);
-    c.scan_total = A.get<long>(1);
-    std::vector<SysCtx> sys(count);
-    for (int i = 0; i < count; ++i) {
-        SysCtx& sc = sys[i];
-        const fx_tree* T = trees[i];
-        sc.T = T;
-        for (int j = 0; j < ndens; ++j) {
-            sc.P[j] = Ps[i * ndens + j];
-            sc.K[j] = Ks[i * ndens + j];
-        }
-        const int S = T->S;
-        const long n = T->n, nn = n * n;
-        if (stats) stats->levels = std::max(stats->levels, (int)T->levels.size());
-        // density norms; with several densities the largest, so that the
-        // screening bounds every density's contribution
-        sc.Pn = A.get<double>((size_t)S * S);
-        fx_launch_pnorm(sc.P[0], n, T->basis.l, T->basis.f0, S, sc.Pn, st);
-        if (ndens > 1) {
-            double* Pn2 = A.get<double>((size_t)S * S);
-            for (int j = 1; j < ndens; ++j) {
-                fx_launch_pnorm(sc.P[j], n, T->basis.l, T->basis.f0, S, Pn2, st);
-                fx_launch_max_inplace(sc.Pn, Pn2, (long)S * S, st);
-            }
-            A.release(Pn2);
-        }
-        const int nl = (int)T->levels.size();
-        sc.Psq.resize(nl);
-        for (int k = nl - 1; k >= 0; --k) {
-            const int nk = (int)T->levels[k].sL.size();
-            sc.Psq[k] = A.get<double>((size_t)nk * nk);
-            if (k == nl - 1)
-                fx_launch_leaf_sq(sc.Pn, S, T->d_sL[k], T->d_sR[k], nk, sc.Psq[k], st);
-            else
-                fx_launch_level_up(sc.Psq[k + 1], (int)T->levels[k + 1].sL.size(), T->d_ch0[k], T->d_nch[k], nk,
-                                   sc.Psq[k], st);
-        }
-        // K symmetry: with a bitwise symmetric P, K_da = K_ad^T, so only the
-        // K blocks on and above the diagonal (tree order) are built.
-        sc.sym = 0;
-        if (o.symmetry == FX_SYM_AUTO && (n + 31) / 32 <= 65535) {
-            int* flag = A.get<int>(1);
-            fx_launch_fill_i32(flag, 1, 0, st);
-            for (int j = 0; j < ndens; ++j) fx_launch_psym(sc.P[j], n, flag, st);
-            sc.sym = read1(flag, st) == 0 ? 1 : 0;
-            A.release(flag);
-        }
-        if (stats) stats->symmetric_systems += sc.sym;
-        sc.slots = A.get<double>((size_t)c.nslot * nn * ndens);
-        fx_launch_fill(sc.slots, (long)c.nslot * nn * ndens, 0.0, st);
-        FX_HIP(hipGetLastError());
-        // root task
-        const double q0 = read1(T->d_Qsq[0], st), p0 = read1(sc.Psq[0], st);
-        if ((q0 * q0) * p0 * (1.0 + 1e-12) > tau * tau) {
-            DevArena R(st);
-            Frontier f{};
-            f.ad = upload(R, std::vector<int2>{make_int2(0, 0)});
-            f.bc_off = upload(R, std::vector<long>{0, 1});
-            f.bc = upload(R, std::vector<int2>{make_int2(0, 0)});
-            f.parent = upload(R, std::vector<int>{0});
-            f.nad = 1;
-            f.e_begin = 0;
-            f.e_count = 1;
-            f.p_base = 0;
-            traverse(c, sc, 0, f);
-        }
-    }
-    if (c.collect) {
-        auto t1 = std::chrono::steady_clock::now();
-        std::vector<LeafSeg*> segs;
-        for (auto& g : c.segs) segs.push_back(g.get());
-        run_classes(c, segs);
-        c.segs.clear();
-        c.seconds_eri += std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
-    }
-    for (int i = 0; i < count; ++i) {
-        const long nn = (long)sys[i].T->n * sys[i].T->n;
-        for (int j = 0; j < ndens; ++j)
-            fx_launch_finalize(sys[i].slots + (long)j * c.nslot * nn, c.nslot, nn, o.alpha, o.beta, sys[i].K[j], st);
-    }
-    FX_HIP(hipGetLastError());
-    struct EvGuard {
-        ExCtx& c;
-        ~EvGuard() {
-            for (auto& t : c.timed) {
-                (void)hipEventDestroy(t.a);
-                (void)hipEventDestroy(t.b);
-            }
-        }
-    } evguard{c};
-    std::vector<unsigned long long> cnt(81 * 2 * 3);
-    FX_HIP(hipMemcpyAsync(cnt.data(), c.counters, sizeof(unsigned long long) * cnt.size(), hipMemcpyDeviceToHost, st));
-    FX_HIP(hipStreamSynchronize(st));
-    if (stats) {
-        for (int cls = 0; cls < 81; ++cls)
-            for (int pr = 0; pr < 2; ++pr) {
-                const unsigned long long q = cnt[(cls * 2 + pr) * 3], pq = cnt[(cls * 2 + pr) * 3 + 1];
-                const unsigned long long qm = cnt[(cls * 2 + pr) * 3 + 2];
-                stats->class_quartets[cls] += (int64_t)q;
-                stats->quartets += (int64_t)q;
-                stats->quartets_covered += (int64_t)(q + qm);
-                if (pr) stats->quartets_fp32 += (int64_t)q;
-                stats->prim_quartets += (double)pq;
-                const double fl = (double)pq * fx_class_vrr_flops[cls] + (double)q * fx_class_hrr_flops[cls];
-                stats->flops += fl;
-                stats->class_flops[cls * 2 + pr] = fl;
-                stats->class_prec_quartets[cls * 2 + pr] = (int64_t)q;
-            }
-        for (auto& t : c.timed) {
-            float ms = 0.f;
-            FX_HIP(hipEventElapsedTime(&ms, t.a, t.b));
-            stats->class_seconds[t.idx] += 1e-3 * ms;
-            stats->class_launches[t.idx] += 1;
-        }
-        stats->seconds_eri = c.seconds_eri;
-        stats->seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        stats->seconds_traversal = stats->seconds_total - c.seconds_eri;
-    }
-}
-
-static void exchange_impl(const fx_tree* T, const double* P, double tau, double* K, const fx_exchange_opts* opts,
-                          fx_stats* stats, hipStream_t st) {
-    exchange_many(&T, &P, &K, 1, 1, tau, opts, stats, st);
-}
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -1167,30 +389,9 @@ fx_status fx_build_quadtree(const fx_shells* shells, const fx_tree_opts* opts, v
     });
 }
 
-fx_status fx_exchange_ex(const fx_tree* tree, const double* P, double tau, double* K, const fx_exchange_opts* opts,
-                         fx_stats* stats, void* stream) {
-    return fx_guard([&] { exchange_impl(tree, P, tau, K, opts, stats, (hipStream_t)stream); });
-}
 
-fx_status fx_exchange(const fx_tree* tree, const double* P, double tau, double* K, void* stream) {
-    return fx_exchange_ex(tree, P, tau, K, nullptr, nullptr, stream);
-}
 
-fx_status fx_exchange_batched(const fx_tree* const* trees, const double* const* P, double* const* K, int32_t count,
-                              double tau, const fx_exchange_opts* opts, fx_stats* stats, void* stream) {
-    return fx_guard([&] {
-        if (count < 0 || (count > 0 && (!trees || !P || !K))) fx_fail(FX_ERR_INVALID_ARG, "bad batch arrays");
-        exchange_many(trees, P, K, count, 1, tau, opts, stats, (hipStream_t)stream);
-    });
-}
 
-fx_status fx_exchange_multi(const fx_tree* tree, const double* const* P, double* const* K, int32_t ndens, double tau,
-                            const fx_exchange_opts* opts, fx_stats* stats, void* stream) {
-    return fx_guard([&] {
-        if (!P || !K) fx_fail(FX_ERR_INVALID_ARG, "P and K must be arrays of ndens device pointers");
-        exchange_many(&tree, P, K, 1, ndens, tau, opts, stats, (hipStream_t)stream);
-    });
-}
 
 int32_t fx_nbf(const fx_tree* tree) { return tree ? tree->n : -1; }
 int32_t fx_nshell(const fx_tree* tree) { return tree ? tree->S : -1; }
@@ -1279,28 +480,6 @@ int32_t fx_class_variants_available(int32_t cls) {
     return fx_class_variants[cls];
 }
 
-fx_status fx_record_task_timings(const fx_tree* tree, const double* P, double tau, const fx_exchange_opts* opts,
-                                 fx_task_timings** out, void* stream) {
-    return fx_guard([&] {
-        if (!out) fx_fail(FX_ERR_INVALID_ARG, "out is NULL");
-        *out = nullptr;
-        if (!tree) fx_fail(FX_ERR_INVALID_ARG, "tree is NULL");
-        hipStream_t st = (hipStream_t)stream;
-        DevArena A(st);
-        double* K = A.get<double>((size_t)tree->n * tree->n);
-        fx_task_timings* rec = new fx_task_timings();
-        g_recording = rec;
-        try {
-            exchange_impl(tree, P, tau, K, opts, nullptr, st);
-        } catch (...) {
-            g_recording = nullptr;
-            delete rec;
-            throw;
-        }
-        g_recording = nullptr;
-        *out = rec;
-    });
-}
 
 fx_status fx_task_timings_create(const float* feats, const float* log2_ns, const int32_t* cls, int64_t n,
                                  fx_task_timings** out) {
@@ -1355,6 +534,59 @@ fx_status fx_costmodel_params(const fx_costmodel* m, float* params, float* norm)
 
 void fx_costmodel_free(fx_costmodel* m) { delete m; }
 
+// File format: the 8 bytes "FXMLP001", two little-endian uint32 (parameter
+// and normalisation counts), then the parameters and the normalisation as
+// little-endian IEEE binary32, in the order of fx_costmodel_params.
+static const char kMlpMagic[8] = {'F', 'X', 'M', 'L', 'P', '0', '0', '1'};
+
+fx_status fx_costmodel_save(const fx_costmodel* m, const char* path) {
+    return fx_guard([&] {
+        if (!m || !path) fx_fail(FX_ERR_INVALID_ARG, "NULL argument");
+        FILE* f = std::fopen(path, "wb");
+        if (!f) fx_fail(FX_ERR_INVALID_ARG, std::string("cannot open ") + path + " for writing");
+        const uint32_t np = FX_MLP_NPARAM, nn = FX_MLP_NNORM;
+        bool ok = std::fwrite(kMlpMagic, 1, 8, f) == 8 && std::fwrite(&np, 4, 1, f) == 1 &&
+                  std::fwrite(&nn, 4, 1, f) == 1 && std::fwrite(m->W.data(), 4, np, f) == np &&
+                  std::fwrite(m->norm.data(), 4, nn, f) == nn;
+        ok = (std::fclose(f) == 0) && ok;
+        if (!ok) fx_fail(FX_ERR_INVALID_ARG, std::string("write to ") + path + " failed");
+    });
+}
+
+fx_status fx_costmodel_load(const char* path, fx_costmodel** out) {
+    return fx_guard([&] {
+        if (!path || !out) fx_fail(FX_ERR_INVALID_ARG, "NULL argument");
+        *out = nullptr;
+        FILE* f = std::fopen(path, "rb");
+        if (!f) fx_fail(FX_ERR_INVALID_ARG, std::string("cannot open ") + path);
+        char magic[8];
+        uint32_t np = 0, nn = 0;
+        std::vector<float> W(FX_MLP_NPARAM), norm(FX_MLP_NNORM);
+        bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMlpMagic, 8) == 0 &&
+                  std::fread(&np, 4, 1, f) == 1 && std::fread(&nn, 4, 1, f) == 1 && np == FX_MLP_NPARAM &&
+                  nn == FX_MLP_NNORM && std::fread(W.data(), 4, np, f) == np && std::fread(norm.data(), 4, nn, f) == nn;
+        char extra;
+        ok = ok && std::fread(&extra, 1, 1, f) == 0;
+        std::fclose(f);
+        if (!ok) fx_fail(FX_ERR_INVALID_ARG, std::string(path) + " is not a cost-model file of this library");
+        for (float v : W)
+            if (!std::isfinite(v)) fx_fail(FX_ERR_INVALID_ARG, "non-finite parameter in the cost-model file");
+        for (int k = 0; k < FX_MLP_NNORM; ++k)
+            if (!std::isfinite(norm[k]) || (k >= 4 && k < 8 && !(norm[k] > 0.f)) || (k == 9 && !(norm[k] > 0.f)))
+                fx_fail(FX_ERR_INVALID_ARG, "invalid normalisation in the cost-model file");
+        fx_costmodel* m = new fx_costmodel();
+        m->W = W;
+        m->norm = norm;
+        try {
+            m->upload();
+        } catch (...) {
+            delete m;
+            throw;
+        }
+        *out = m;
+    });
+}
+
 int32_t fx_costmodel_nparams(void) { return FX_MLP_NPARAM; }
 
 fx_status fx_costmodel_predict(const fx_costmodel* m, const float* feats, int64_t n, float* out, void* stream) {
@@ -1366,7 +598,7 @@ fx_status fx_costmodel_predict(const fx_costmodel* m, const float* feats, int64_
         float4* f = A.get<float4>(n);
         float* y = A.get<float>(n);
         FX_HIP(hipMemcpyAsync(f, feats, sizeof(float4) * n, hipMemcpyHostToDevice, st));
-        fx_launch_mlp_predict(m->dW, m->dnorm, f, n, y, st);
+        fx_launch_mlp_predict(m->dW, m->dnorm, f, nullptr, n, y, st);
         FX_HIP(hipMemcpyAsync(out, y, sizeof(float) * n, hipMemcpyDeviceToHost, st));
         FX_HIP(hipStreamSynchronize(st));
     });

@@ -49,6 +49,31 @@ struct FxDevBasis {
     const FxPrimPair* pp; // [Nt*Nt] primitive-pair records, (global prim i, global prim j)
 };
 
+#define FX_MAX_LEVELS 32
+
+// Sizes of one traversal chunk of one system, produced and read on the
+// device (the host never needs them to launch the next step).
+struct FxDevCounts {
+    long nad[FX_MAX_LEVELS];          // (A, D) pairs at each level
+    long ne[FX_MAX_LEVELS];           // (B, C) entries at each level
+    long tot[2];                      // scan totals (entries, ADs) of the level being expanded
+    long ubase[10];                   // unit list bounds per (la, ld): units of la*3+ld in [ubase[k], ubase[k+1])
+    long need;                        // entries requested by a level that exceeded its capacity
+    int need_level;                   // that level
+    int overflow;                     // a level exceeded its capacity: this chunk's K blocks are incomplete
+    int sym;                          // 1: symmetric density, only K blocks a <= d are built
+};
+
+// Totals of one call over its systems and traversal chunks (device).
+struct FxDevRun {
+    long e_in, e_leaf;                // largest inner / leaf entry counts of a chunk (next call's capacities)
+    long need_in, need_leaf;          // largest requests of an inner / the leaf level that exceeded its capacity
+    int overflow;                     // some chunk exceeded a capacity (its K is NaN)
+    int pad;
+    long frontier[FX_MAX_LEVELS];     // entries per level, summed over the completed chunks
+    long items, units;                // leaf (A, D) items and K-block units, summed
+};
+
 // One system (or traversal chunk) as seen by the class kernels.
 struct FxSys {
     FxDevBasis basis;
@@ -58,9 +83,9 @@ struct FxSys {
     const long* bc_off;               // per leaf item: offsets into bc
     const int2* bc;                   // (B, C) leaf nodes
     const long* cls_off;              // single-shell leaves: per item 10 class offsets, else null
-    double* slots;                    // K slots of this system, n*n each; density j's at slots + j*slot_stride
-    long slot_stride;
-    int sym;                          // 1: only units a <= d (tree order) exist; each writes K_ad and K_da
+    double* acc[FX_MAX_DENS];         // K accumulator of each density (n x n, caller order)
+    const FxDevCounts* cnt;           // sizes; cnt->sym = 1: only units a <= d (tree order) exist and each
+                                      // writes K_ad and K_da
 };
 
 // launch options (autotuned per class and precision)
@@ -81,11 +106,12 @@ struct FxClassArgs {
     const FxSys* sys;                 // batched launches: per-unit system descriptors
     const int* unit_sys;              // batched launches: system of every unit
     const double* boys;
-    const int* units;                 // [3*nunits] (item, a, d)
-    const int* order;                 // schedule permutation of units, or null
-    long nunits;
-    int slot_index;                   // K slot of this (lb, lc, precision)
+    const int* units;                 // unit list (item, a, d), 3 ints per unit
+    const long* ulh;                  // device {lo, hi}: this launch's units are units[lo..hi)
+    long nbound;                      // host bound of hi - lo (the grid size)
+    const int* order;                 // schedule permutation of units (relative to lo), or null
     double tau, thr;
+    int block;                        // 1: leaf_screen BLOCK, every quartet of a surviving leaf task
     int mode;                         // FX_MODE_*
     int flags;                        // FX_LAUNCH_*
     int ndens;                        // densities per system (1 or 2)

@@ -439,7 +439,7 @@ def _emit_vrr(w, vem, tpos0, nj, ind, put_fmt):
         put(nm)
 
 
-def _emit_fold(w, real, o, comps, icomp, fcols, idx):
+def _emit_fold(w, real, o, comps, icomp, fcols, idx, preamble=True, ucount=None):
     """Steps 2+3 of the folded staged routine: per ket column f, the bra HRR
     of X[., f] into registers, then every (x3 x4) component whose closed-form
     ket HRR uses column f adds (x1 x2|f) * coef * P into kacc."""
@@ -447,15 +447,16 @@ def _emit_fold(w, real, o, comps, icomp, fcols, idx):
     nd = len(comps[3])
     index = [{t: k for k, t in enumerate(comps[r])} for r in range(4)]
     nkb = len(comps[0]) * nd
-    for jn, nu in enumerate(comps[1]):
+    for jn, nu in (enumerate(comps[1]) if preamble else []):
         for kl, lam in enumerate(comps[2]):
             fac = comp_factor(nu) * comp_factor(lam)
             scale = "" if abs(fac - 1.0) < 1e-15 else f" * {fac!r}"
             w(f"  double pv{jn}_{kl}[NDENS];")
             w(f"  FX_FOR_DENS pv{jn}_{kl}[_d] = Pq[_d][{jn} * ldp + {kl}]{scale};")
             fl += 1 if scale else 0
-    w("  const double CDx2 = CDx * CDx, CDy2 = CDy * CDy, CDz2 = CDz * CDz;")
-    w("  (void)CDx2; (void)CDy2; (void)CDz2;")
+    if preamble:
+        w("  const double CDx2 = CDx * CDx, CDy2 = CDy * CDy, CDz2 = CDz * CDz;")
+        w("  (void)CDx2; (void)CDy2; (void)CDz2;")
     powname = {1: "CD{}", 2: "CD{}2"}
     for f in fcols:
         hem = Emitter(real)
@@ -477,7 +478,7 @@ def _emit_fold(w, real, o, comps, icomp, fcols, idx):
         for line in hem.lines:
             w("    " + line)
         fl += hem.flops
-        nu_ = 0
+        nu_ = ucount[0] if ucount else 0
         for t3 in icomp[2]:
             for t4 in icomp[3]:
                 k = tuple(f[i] - t3[i] for i in range(3))
@@ -513,6 +514,8 @@ def _emit_fold(w, real, o, comps, icomp, fcols, idx):
                           f"FX_FOR_DENS kacc[_d * {nkb} + {im * nd + ls_}] += _v * {us[key]}[_d]; }}")
                         fl += 2
         w("  }")
+        if ucount:
+            ucount[0] = nu_
     return fl
 
 
@@ -706,6 +709,108 @@ def gen_class_staged(la, lb, lc, ld, real, paired=False, fold=False):
     return "\n".join(out), vem.flops, hflops
 
 
+def gen_class_chunked(la, lb, lc, ld, real, nchunks, paired=True, xreg=False):
+    """Folded staged routine with the ket columns in nchunks chunks: for each
+    chunk the primitive loop rebuilds only that chunk's [e0|f0] columns (the
+    VRR of the other columns' ancestors is recomputed), then folds them into
+    kacc.  The live [e0|f0] slice is 1/nchunks of the block."""
+    ls = (la, lb, lc, ld)
+    o = orientation(la, lb, lc, ld)
+    L = [ls[x] for x in o]
+    l1, l2, l3, l4 = L
+    Lsum = sum(L)
+    comps = [cart(l) for l in ls]
+    icomp = [cart(l) for l in L]
+    fcols = [f for lf in range(L[2], L[2] + L[3] + 1) for f in cart(lf)]
+    erows = [e for le in range(l1, l1 + l2 + 1) for e in cart(le)]
+    chunks = [fcols[c * len(fcols) // nchunks:(c + 1) * len(fcols) // nchunks] for c in range(nchunks)]
+    NX = max(len(erows) * len(ch) for ch in chunks)
+    out = []
+    w = out.append
+    cls = f"{LNAME[la]}{LNAME[lb]}{LNAME[lc]}{LNAME[ld]}"
+    prec = "f32" if real == "float" else "f64"
+    w(f"// class ({cls}) {prec}, staged in {nchunks} ket-column chunks; X {NX}")
+    w("template <int NDENS>")
+    w(f"__device__ __forceinline__ void eri_{cls}_{prec}(const FxShellRef& ra, const FxShellRef& rb, const FxShellRef& rc,")
+    w(f"    const FxShellRef& rd, const FxDevBasis& B,")
+    w(f"    const double* __restrict__ boys_tab, const double* const* __restrict__ Pq, long ldp, double* __restrict__ kacc) {{")
+    roles = ["ra", "rb", "rc", "rd"]
+    x = [roles[r] for r in o]
+    w(f"  const FxShellRef& x1 = {x[0]}; const FxShellRef& x2 = {x[1]}; const FxShellRef& x3 = {x[2]}; const FxShellRef& x4 = {x[3]};")
+    if xreg:
+        w(f"  {real} X[{NX}];")
+    else:
+        w(f"  {real} Xs[{NX}];")
+        w(f"  __attribute__((address_space(5))) {real}* X = (__attribute__((address_space(5))) {real}*)Xs;")
+        w("  asm volatile(\"\" : \"+v\"(X));")
+    w("  const double ABx = x1.x - x2.x, ABy = x1.y - x2.y, ABz = x1.z - x2.z;")
+    w("  const double CDx = x3.x - x4.x, CDy = x3.y - x4.y, CDz = x3.z - x4.z;")
+    w("  const long Nt = B.ntprim;")
+    w("  const FxPrimPair* __restrict__ pab = B.pp + (long)x1.pofs * Nt + x2.pofs;")
+    w("  const FxPrimPair* __restrict__ pcd = B.pp + (long)x3.pofs * Nt + x4.pofs;")
+    w(f"  const {real} ABx_ = ({real})ABx, ABy_ = ({real})ABy, ABz_ = ({real})ABz;")
+    w(f"  const {real} CDx_ = ({real})CDx, CDy_ = ({real})CDy, CDz_ = ({real})CDz;")
+    w("  (void)ABx_; (void)ABy_; (void)ABz_; (void)CDx_; (void)CDy_; (void)CDz_;")
+    # P factors and CD powers once
+    for jn, nu in enumerate(comps[1]):
+        for kl, lam in enumerate(comps[2]):
+            fac = comp_factor(nu) * comp_factor(lam)
+            scale = "" if abs(fac - 1.0) < 1e-15 else f" * {fac!r}"
+            w(f"  double pv{jn}_{kl}[NDENS];")
+            w(f"  FX_FOR_DENS pv{jn}_{kl}[_d] = Pq[_d][{jn} * ldp + {kl}]{scale};")
+    w("  const double CDx2 = CDx * CDx, CDy2 = CDy * CDy, CDz2 = CDz * CDz;")
+    w("  (void)CDx2; (void)CDy2; (void)CDz2;")
+    ucount = [0]
+    vfl = 0
+    for ci, ch in enumerate(chunks):
+        vem = Emitter(real)
+        vrr = VRR(vem)
+        targets = [(e, f) for e in erows for f in ch]
+        tnames = [vrr.get(e, f, 0) for (e, f) in targets]
+        vfl += vem.flops
+        tpos0 = {nm: k for k, nm in enumerate(tnames)}
+        idx = {t: k for k, t in enumerate(targets)}
+        w(f"  {{  // ket columns {ci}")
+
+        def setup(j, ind, wexpr=None):
+            _emit_prim_setup(w, real, Lsum, j, ind, wexpr)
+
+        def vrr_lines(nj, ind, vem=vem, tpos0=tpos0):
+            _emit_vrr(w, vem, tpos0, nj, ind,
+                      lambda k, sm: f"if constexpr (ACC) X[{k}] += {sm}; else X[{k}] = {sm};")
+        if paired:
+            w("  const int n4 = x4.nprim, n34 = x3.nprim * n4, n234 = x2.nprim * n34;")
+            w("  const int nq = x1.nprim * n234;")
+            w("  auto prim2 = [&](int qa, int qb, double wb, auto acc) {")
+            w("    constexpr bool ACC = decltype(acc)::value;")
+            for j, qv in ((0, "qa"), (1, "qb")):
+                w(f"    const int i1_{j} = {qv} / n234, i2_{j} = ({qv} / n34) % x2.nprim, i3_{j} = ({qv} / n4) % x3.nprim, "
+                  f"i4_{j} = {qv} % n4;")
+            setup(0, "    ")
+            setup(1, "    ", "wb")
+            vrr_lines(2, "    ")
+            w("  };")
+            w("  prim2(0, nq > 1 ? 1 : 0, nq > 1 ? 1.0 : 0.0, FxAcc<false>{});")
+            w("  for (int q = 2; q < nq; q += 2)")
+            w("    prim2(q, q + 1 < nq ? q + 1 : q, q + 1 < nq ? 1.0 : 0.0, FxAcc<true>{});")
+        else:
+            w("  auto prim = [&](int i1_0, int i2_0, int i3_0, int i4_0, auto acc) {")
+            w("    constexpr bool ACC = decltype(acc)::value;")
+            setup(0, "    ")
+            vrr_lines(1, "    ")
+            w("  };")
+            w("  prim(0, 0, 0, 0, FxAcc<false>{});")
+            w("  for (int i1 = 0; i1 < x1.nprim; ++i1)")
+            w("    for (int i2 = 0; i2 < x2.nprim; ++i2)")
+            w("      for (int i3 = 0; i3 < x3.nprim; ++i3)")
+            w("        for (int i4 = 0; i4 < x4.nprim; ++i4)")
+            w("          if (i1 | i2 | i3 | i4) prim(i1, i2, i3, i4, FxAcc<true>{});")
+        _emit_fold(w, real, o, comps, icomp, ch, idx, preamble=False, ucount=ucount)
+        w("  }")
+    w("}")
+    return "\n".join(out), vfl
+
+
 def classes():
     return list(itertools.product(range(3), repeat=4))
 
@@ -777,6 +882,13 @@ MIN_WAVES = {("dddd", "f64"): 3} | {(c, "f64"): 2 for c in ("ddds", "ddsd", "dsd
 MIN_WAVES.update({(c, "mix"): 2 for c in ("sdsd", "dsds", "dssd", "dsss", "spss")})
 
 
+# Staged classes whose primitive loop runs once per chunk of ket columns
+# (gen_class_chunked), by number of chunks: only that chunk's [e0|f0]
+# columns are live, at the price of recomputing the VRR of their shared
+# ancestors in every chunk.
+CHUNKS = {}
+
+
 def variants(la, lb, lc, ld):
     nacc = pair_size(la, lb) * pair_size(lc, ld)
     return (nacc < THREAD_MAX, nacc >= COOP_MIN)
@@ -792,9 +904,12 @@ def main(outdir):
         parts = []
         for real in ("double", "float"):
             code, fp, fc = gen_class(la, lb, lc, ld, real)
-            if (cls, "f32" if real == "float" else "f64") in STAGED:
+            prec = "f32" if real == "float" else "f64"
+            if (cls, prec) in CHUNKS:
+                code = gen_class_chunked(la, lb, lc, ld, real, CHUNKS[(cls, prec)], paired=cls not in UNPAIRED)[0]
+            elif (cls, prec) in STAGED:
                 code = gen_class_staged(la, lb, lc, ld, real, paired=cls not in UNPAIRED,
-                                        fold=(cls, "f32" if real == "float" else "f64") in FOLD)[0]
+                                        fold=(cls, prec) in FOLD)[0]
             if th:
                 parts.append(code)
             if real == "double":

@@ -18,6 +18,7 @@ _lib = None
 FX_PREC_FP64, FX_PREC_MIXED = 0, 1
 FX_SCHED_BOUND, FX_SCHED_MLP, FX_SCHED_NONE = 0, 1, 2
 FX_SYM_AUTO, FX_SYM_OFF = 0, 1
+FX_LEAF_SHELL, FX_LEAF_BLOCK = 0, 1
 
 
 class FxError(RuntimeError):
@@ -41,7 +42,7 @@ class fx_exchange_opts(ctypes.Structure):
                 ("schedule", ctypes.c_int32), ("costmodel", ctypes.c_void_p),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("max_frontier_entries", ctypes.c_int64), ("profile", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("symmetry", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("symmetry", ctypes.c_int32), ("leaf_screen", ctypes.c_int32)]
 
 
 class fx_train_opts(ctypes.Structure):
@@ -59,7 +60,8 @@ class fx_stats(ctypes.Structure):
                 ("class_flops", ctypes.c_double * 162), ("class_prec_quartets", ctypes.c_int64 * 162),
                 ("seconds_traversal", ctypes.c_double), ("seconds_eri", ctypes.c_double),
                 ("seconds_total", ctypes.c_double), ("quartets_covered", ctypes.c_int64),
-                ("symmetric_systems", ctypes.c_int32)]
+                ("symmetric_systems", ctypes.c_int32), ("partition", ctypes.c_int64 * 3),
+                ("overflow", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {"levels": self.levels, "frontier": list(self.frontier)[: self.levels],
@@ -71,13 +73,15 @@ class fx_stats(ctypes.Structure):
                 "seconds_traversal": self.seconds_traversal, "seconds_eri": self.seconds_eri,
                 "seconds_total": self.seconds_total, "quartets_covered": self.quartets_covered,
                 "symmetric_systems": self.symmetric_systems,
+                "partition": [int(x) for x in self.partition],
+                "overflow": int(self.overflow), "workspace_bytes": int(self.workspace_bytes),
                 "class_seconds": np.array(self.class_seconds).reshape(81, 2),
                 "class_launches": np.array(self.class_launches).reshape(81, 2),
                 "class_flops": np.array(self.class_flops).reshape(81, 2),
                 "class_prec_quartets": np.array(self.class_prec_quartets, dtype=np.int64).reshape(81, 2)}
 
 
-EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_batched", "fx_exchange_multi", "fx_nbf",
+EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_opts_init", "fx_exchange_batched", "fx_exchange_multi", "fx_nbf",
             "fx_nshell",
             "fx_tree_perm", "fx_tree_levels", "fx_tree_schwarz", "fx_tree_free", "fx_set_allocator",
             "fx_status_string", "fx_last_error_message", "fx_plan_tree", "fx_hilbert_key3",
@@ -85,7 +89,8 @@ EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_b
             "fx_set_class_launch", "fx_get_class_launch", "fx_xcd_block",
             "fx_record_task_timings", "fx_task_timings_create", "fx_task_timings_count", "fx_task_timings_get",
             "fx_task_timings_free", "fx_costmodel_train", "fx_costmodel_nparams", "fx_costmodel_create",
-            "fx_costmodel_params", "fx_costmodel_predict", "fx_costmodel_loss_grad", "fx_costmodel_free"]
+            "fx_costmodel_params", "fx_costmodel_predict", "fx_costmodel_loss_grad", "fx_costmodel_free",
+            "fx_costmodel_save", "fx_costmodel_load"]
 
 
 def lib():
@@ -105,6 +110,8 @@ def lib():
                                       ctypes.POINTER(fx_exchange_opts), ctypes.POINTER(fx_stats), vp]
     L.fx_exchange_multi.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl,
                                     ctypes.POINTER(fx_exchange_opts), ctypes.POINTER(fx_stats), vp]
+    L.fx_exchange_opts_init.argtypes = [ctypes.POINTER(fx_exchange_opts)]
+    L.fx_exchange_opts_init.restype = None
     for f in ("fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_batched", "fx_exchange_multi", "fx_tree_perm",
               "fx_tree_schwarz", "fx_set_allocator", "fx_plan_tree"):
         getattr(L, f).restype = ctypes.c_int
@@ -153,8 +160,11 @@ def lib():
     L.fx_costmodel_loss_grad.argtypes = [vp, fp, fp, i64, fp, fp, vp]
     L.fx_costmodel_free.argtypes = [vp]
     L.fx_costmodel_free.restype = None
+    L.fx_costmodel_save.argtypes = [vp, ctypes.c_char_p]
+    L.fx_costmodel_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
     for f in ("fx_record_task_timings", "fx_task_timings_create", "fx_task_timings_get", "fx_costmodel_train",
-              "fx_costmodel_create", "fx_costmodel_params", "fx_costmodel_predict", "fx_costmodel_loss_grad"):
+              "fx_costmodel_create", "fx_costmodel_params", "fx_costmodel_predict", "fx_costmodel_loss_grad",
+              "fx_costmodel_save", "fx_costmodel_load"):
         getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -260,12 +270,20 @@ def build_quadtree_from(system, **kw) -> Tree:
     return fx_build_quadtree(system.l, system.nprim, system.center, system.exps, system.coefs, **kw)
 
 
+def opts_init():
+    """The library's defaults (fx_exchange_opts_init)."""
+    o = fx_exchange_opts()
+    lib().fx_exchange_opts_init(ctypes.byref(o))
+    return o
+
+
 def make_opts(precision=FX_PREC_FP64, fp32_threshold=1e-5, schedule=FX_SCHED_BOUND, costmodel=None, alpha=1.0,
-              beta=0.0, max_frontier_entries=0, profile=False, use_graph=False, symmetry=FX_SYM_AUTO):
+              beta=0.0, max_frontier_entries=0, profile=False, use_graph=False, symmetry=FX_SYM_AUTO,
+              leaf_screen=FX_LEAF_SHELL):
     return fx_exchange_opts(int(precision), float(fp32_threshold), int(schedule),
                             ctypes.c_void_p(costmodel.handle if costmodel is not None else None),
                             float(alpha), float(beta), int(max_frontier_entries), int(bool(profile)),
-                            int(bool(use_graph)), int(symmetry))
+                            int(bool(use_graph)), int(symmetry), int(leaf_screen))
 
 
 def fx_exchange(tree: Tree, P, tau, K, stream=None):
@@ -277,19 +295,21 @@ def fx_exchange(tree: Tree, P, tau, K, stream=None):
     return K
 
 
-def fx_exchange_ex(tree: Tree, P, tau, K, opts=None, stream=None):
+def fx_exchange_ex(tree: Tree, P, tau, K, opts=None, stream=None, stats=True):
+    """With stats=True the call waits and returns (K, stats); with
+    stats=False it only enqueues the work and returns (K, None)."""
     n = tree.nbf
     _check_matrix(P, n, "P")
     _check_matrix(K, n, "K")
-    st = fx_stats()
+    st = fx_stats() if stats else None
     o = opts if opts is not None else make_opts()
     _check(lib().fx_exchange_ex(tree.handle, ctypes.c_void_p(P.data_ptr()), float(tau),
-                                ctypes.c_void_p(K.data_ptr()), ctypes.byref(o), ctypes.byref(st),
-                                _stream_ptr(stream)))
-    return K, st.as_dict()
+                                ctypes.c_void_p(K.data_ptr()), ctypes.byref(o),
+                                ctypes.byref(st) if st is not None else None, _stream_ptr(stream)))
+    return K, (st.as_dict() if st is not None else None)
 
 
-def fx_exchange_batched(trees, Ps, Ks, tau, opts=None, stream=None):
+def fx_exchange_batched(trees, Ps, Ks, tau, opts=None, stream=None, stats=True):
     count = len(trees)
     for t, P, K in zip(trees, Ps, Ks):
         _check_matrix(P, t.nbf, "P")
@@ -298,11 +318,11 @@ def fx_exchange_batched(trees, Ps, Ks, tau, opts=None, stream=None):
     th = VP(*[t.handle for t in trees])
     ph = VP(*[P.data_ptr() for P in Ps])
     kh = VP(*[K.data_ptr() for K in Ks])
-    st = fx_stats()
+    st = fx_stats() if stats else None
     o = opts if opts is not None else make_opts()
-    _check(lib().fx_exchange_batched(th, ph, kh, count, float(tau), ctypes.byref(o), ctypes.byref(st),
-                                     _stream_ptr(stream)))
-    return Ks, st.as_dict()
+    _check(lib().fx_exchange_batched(th, ph, kh, count, float(tau), ctypes.byref(o),
+                                     ctypes.byref(st) if st is not None else None, _stream_ptr(stream)))
+    return Ks, (st.as_dict() if st is not None else None)
 
 
 def fx_exchange_multi(tree: Tree, Ps, Ks, tau, opts=None, stream=None):
@@ -425,6 +445,15 @@ class CostModel:
         nm = np.ascontiguousarray(norm, np.float32)
         h = ctypes.c_void_p()
         _check(lib().fx_costmodel_create(_fptr(w), _fptr(nm), ctypes.byref(h)))
+        return CostModel(h.value)
+
+    def save(self, path):
+        _check(lib().fx_costmodel_save(self._h, os.fsencode(path)))
+
+    @staticmethod
+    def load(path):
+        h = ctypes.c_void_p()
+        _check(lib().fx_costmodel_load(os.fsencode(path), ctypes.byref(h)))
         return CostModel(h.value)
 
     def predict(self, feats, stream=None):

@@ -1,0 +1,106 @@
+"""Asynchronous calls, whole-call graph capture and replay, and buffer
+capacities (the traversal of Eqs. 7a-d keeps every size on the device)."""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+fx = pytest.importorskip("paper_1401_6961_amd")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def mid():
+    """250-atom s+p+d cluster (about a second per build) and its reference K."""
+    s = synthetic.cluster(250, seed=2250)
+    tree = fx.build_quadtree_from(s)
+    P = torch.from_numpy(s.P).cuda()
+    Kref, st = fx.fx_exchange_ex(tree, P, s.tau, torch.zeros_like(P), fx.make_opts(precision=fx.FX_PREC_MIXED))
+    torch.cuda.synchronize()
+    return s, tree, P, Kref.clone(), st
+
+
+def test_call_returns_before_K_is_complete(mid):
+    s, tree, P, Kref, st = mid
+    say("gpu: asynchronous call")
+    K = torch.full_like(P, 7.0)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    fx.fx_exchange_ex(tree, P, s.tau, K, fx.make_opts(precision=fx.FX_PREC_MIXED), stats=False)
+    pending = not stream.query()
+    torch.cuda.synchronize()
+    assert pending, "the call waited for its work"
+    assert torch.equal(K, Kref)
+
+
+def test_plain_fx_exchange_is_asynchronous_and_exact(mid):
+    s, tree, P, _, _ = mid
+    say("gpu: fx_exchange (FP64 defaults)")
+    K64, _ = fx.fx_exchange_ex(tree, P, s.tau, torch.zeros_like(P))
+    K = torch.zeros_like(P)
+    fx.fx_exchange(tree, P, s.tau, K)
+    torch.cuda.synchronize()
+    assert torch.equal(K, K64)
+
+
+def test_graph_replays_equal_eager(mid):
+    """The whole call (norms, traversal, units, class kernels, scaling)
+    captured once and replayed: every replay equals the eager result
+    bitwise, with eager work and synchronisations between replays."""
+    s, tree, P, Kref, _ = mid
+    say("gpu: graph capture and replays")
+    opts = fx.make_opts(precision=fx.FX_PREC_MIXED, use_graph=True)
+    K = torch.zeros_like(P)
+    for i in range(4):
+        K.fill_(float(i + 1))
+        fx.fx_exchange_ex(tree, P, s.tau, K, opts, stats=False)
+        torch.cuda.synchronize()
+        assert torch.equal(K, Kref), f"replay {i}"
+        # eager work of the program between replays
+        Ke, _ = fx.fx_exchange_ex(tree, P, s.tau, torch.zeros_like(P), fx.make_opts(precision=fx.FX_PREC_MIXED))
+        torch.cuda.synchronize()
+        assert torch.equal(Ke, Kref)
+    # with statistics the replay is also checked for capacity on the host
+    K2, st = fx.fx_exchange_ex(tree, P, s.tau, torch.zeros_like(P), opts)
+    assert st["graph_nodes"] == 1 and st["overflow"] == 0
+    assert torch.equal(K2, Kref)
+
+
+def test_overflow_without_waiting_gives_nan_and_waiting_splits(mid):
+    """A capacity too small for the traversal: a call that does not wait
+    writes NaN (never a silently wrong K); a call that waits splits its K
+    rows and returns the exact K."""
+    s, tree, P, Kref, st0 = mid
+    cap = max(st0["frontier"]) // 4      # a quarter of the largest level: row ranges must split
+    say(f"gpu: capacity overflow (asynchronous and waiting), cap {cap} of {max(st0['frontier'])}")
+    small = fx.make_opts(precision=fx.FX_PREC_MIXED, max_frontier_entries=cap)
+    K = torch.zeros_like(P)
+    fx.fx_exchange_ex(tree, P, s.tau, K, small, stats=False)
+    torch.cuda.synchronize()
+    assert torch.isnan(K).all()
+    K2, st = fx.fx_exchange_ex(tree, P, s.tau, torch.zeros_like(P), small)
+    assert st["chunks"] > 0 and st["overflow"] == 1      # split after an overflow; K complete
+    assert torch.equal(K2, Kref)
+    assert st["quartets"] == st0["quartets"]
+
+
+def test_first_call_learns_capacities():
+    """A fresh tree: the first call sizes its buffers by a traversal-only
+    pass; later calls need no more than 25% above the sizes seen."""
+    s = synthetic.chain(200)
+    tree = fx.build_quadtree_from(s)
+    P = torch.from_numpy(s.P).cuda()
+    say("gpu: capacity learning on a fresh tree")
+    K1 = torch.zeros_like(P)
+    fx.fx_exchange(tree, P, s.tau, K1)
+    K2, st = fx.fx_exchange_ex(tree, P, s.tau, torch.zeros_like(P))
+    torch.cuda.synchronize()
+    assert torch.equal(K1, K2) and st["overflow"] == 0 and st["chunks"] == 0
+    Ko, _ = oracle.exchange(s)
+    assert np.abs(K2.cpu().numpy() - Ko).max() <= 1e-10

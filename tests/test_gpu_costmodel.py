@@ -96,8 +96,8 @@ def _r2(pred, y):
 
 def test_learned_model_predicts_unit_time_better_than_bound_only(recorded):
     """Ablation of the learned part: on a held-out system the MLP's predicted
-    unit times explain the measured ones at least as well as the bound-only
-    estimate (given the benefit of an optimal affine fit)."""
+    unit times explain the measured ones better than the bound-only estimate
+    does, even with that estimate given the benefit of an optimal affine fit."""
     s, tree, P, rec = recorded
     say("gpu: learned vs bound-only prediction on a held-out system")
     m, _ = fx.fx_costmodel_train(rec, steps=1500, batch=8192)
@@ -112,4 +112,16 @@ def test_learned_model_predicts_unit_time_better_than_bound_only(recorded):
     coef = np.linalg.lstsq(A, t1, rcond=None)[0]
     r2_bound = _r2(coef[0] * (f2[:, 0] + f2[:, 1] + f2[:, 3]) + coef[1], t2)
     say(f"R^2 held-out: mlp {r2_mlp:.3f}  bound-only {r2_bound:.3f}")
-    assert r2_mlp >= r2_bound - 0.02
+    assert r2_mlp > r2_bound
+
+
+def test_costmodel_save_load_roundtrip(tmp_path):
+    say("gpu: costmodel save/load")
+    p, norm, f, _ = rand_model(5)
+    m = fx.CostModel.create(p, norm)
+    path = tmp_path / "m.fxmlp"
+    m.save(str(path))
+    m2 = fx.CostModel.load(str(path))
+    w2, n2 = m2.params()
+    assert np.array_equal(w2, p) and np.array_equal(n2, norm)
+    assert np.array_equal(m2.predict(f), m.predict(f))

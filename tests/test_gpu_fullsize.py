@@ -170,3 +170,35 @@ def test_slab_4000_sp_mlp_schedule(slab):
     torch.cuda.synchronize()
     w_, nz = compare_blocks(s, K.cpu().numpy(), pairs, ref, 1e-7)
     say(f"gpu fullsize: slab max err {w_:.2e} over {len(pairs)} blocks ({nz} non-negligible)")
+
+
+def _exact_counts(s, name):
+    """Symmetry off: every ordered quartet is evaluated by its own class
+    kernel, so the per-class counts and the primitive-quartet total must equal
+    the oracle's exhaustive count exactly, and no quartet may lie within
+    1e-10 relative of tau (threshold flips between the two sides)."""
+    tree = fx.build_quadtree_from(s)
+    P = torch.from_numpy(s.P).cuda()
+    say(f"gpu fullsize: {name} counts, GPU build with symmetry off")
+    _, st = fx.fx_exchange_ex(tree, P, s.tau, torch.zeros_like(P),
+                              fx.make_opts(precision=fx.FX_PREC_MIXED, symmetry=fx.FX_SYM_OFF))
+    torch.cuda.synchronize()
+    say(f"gpu fullsize: {name} counts, oracle")
+    cnt, prim, near = oracle.count(s)
+    say(f"gpu fullsize: {name} {int(cnt.sum())} quartets, {near} near tau; GPU {st['quartets']}")
+    assert near == 0
+    assert np.array_equal(st["class_quartets"], cnt)
+    assert st["quartets"] == st["quartets_covered"] == int(cnt.sum())
+    assert st["prim_quartets"] == prim
+    n4 = s.nbf ** 4
+    assert sum(st["partition"]) == n4 and st["partition"][2] == 0
+
+
+@pytest.mark.timeout(900)
+def test_cluster_1000_exact_quartet_counts(cluster):
+    _exact_counts(cluster[0], "cluster")
+
+
+@pytest.mark.timeout(900)
+def test_slab_4000_exact_quartet_counts(slab):
+    _exact_counts(slab[0], "slab")

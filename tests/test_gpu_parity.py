@@ -264,3 +264,52 @@ def test_one_pass_mixed_matches_two_passes(spd5):
     assert np.array_equal(st1["class_prec_quartets"], st2["class_prec_quartets"])
     assert np.abs(K1 - K2).max() <= 1e-12
     assert np.abs(K1 - Ko).max() <= 1e-7 and np.abs(K2 - Ko).max() <= 1e-7
+
+
+@pytest.mark.parametrize("which", ["cube24", "chain200", "chain200_chunked", "spd5_tau_large"])
+def test_traversal_partition_covers_n4(which, chain):
+    """Eqs. (7a-d): the level-by-level expansion visits the product of the
+    four basis trees as a partition -- every task (A,B,C,D) is a surviving
+    leaf task, culled, or (symmetric form) the mirror of a traversed task --
+    so the sums of |A||B||C||D| over the three sets add up to n^4, with and
+    without the symmetric form and with chunked levels."""
+    if which == "cube24":
+        s, tau, extra = synthetic.config(0), None, {}
+    elif which.startswith("chain200"):
+        s, tau = chain[0], None
+        extra = {"max_frontier_entries": 2000} if which.endswith("chunked") else {}
+    else:
+        s, tau, extra = spd_cube(5, 4.0, 31), 1e-3, {}
+    tau = s.tau if tau is None else tau
+    n4 = s.nbf ** 4
+    say(f"gpu: traversal partition {which} n={s.nbf} tau={tau}")
+    for sym in (fx.FX_SYM_OFF, fx.FX_SYM_AUTO):
+        _, st, _ = gpu_exchange(s, tau, symmetry=sym, **extra)
+        leaf, culled, mirrored = st["partition"]
+        assert leaf + culled + mirrored == n4, (sym, st["partition"], n4)
+        assert leaf > 0
+        if sym == fx.FX_SYM_OFF:
+            assert mirrored == 0
+        else:
+            assert st["symmetric_systems"] == 1 and mirrored > 0
+        if extra:
+            assert st["chunks"] > 0
+
+
+@pytest.mark.parametrize("which,leaf", [("cube24", 4), ("cube24", 10), ("spd5", 10)])
+def test_leaf_block_mode_matches_oracle(which, leaf):
+    """leaf_screen BLOCK (the paper's rule: whole leaf blocks of a kept leaf
+    task are computed) against the oracle's own bisection and leaf test, in
+    caller shell order, with and without the symmetric form."""
+    s = synthetic.config(0) if which == "cube24" else spd_cube(5, 4.0, 31)
+    tau = 1e-6
+    say(f"gpu: leaf-block mode {which} leaf={leaf} tau={tau}")
+    Ko, sto = oracle.exchange_leafblock(s, leaf, tau=tau)
+    assert sto["near_threshold"] == 0
+    Ks, sts = oracle.exchange(s, tau=tau)
+    assert sto["quartets"] > sts["quartets"]          # the rule computes more than the shell-level one
+    tree = fx.build_quadtree_from(s, leaf_max_functions=leaf, ordering=1)
+    for sym in (fx.FX_SYM_OFF, fx.FX_SYM_AUTO):
+        Kg, st, _ = gpu_exchange(s, tau, tree=tree, leaf_screen=fx.FX_LEAF_BLOCK, symmetry=sym)
+        assert st["quartets_covered"] == sto["quartets"], (sym, st["quartets_covered"], sto["quartets"])
+        assert np.abs(Kg - Ko).max() <= TOL64

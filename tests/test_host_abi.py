@@ -158,3 +158,31 @@ def test_xcd_remap_is_a_bijection():
 def test_persistent_launch_flag_is_switched_off():
     with pytest.raises(fx.FxError):
         fx.fx_set_class_launch(0, 0, 2)
+
+
+def test_exchange_opts_init_fills_documented_defaults():
+    """A zero-filled options struct is not the defaults (alpha would be 0);
+    fx_exchange_opts_init gives the documented ones."""
+    o = fx.opts_init()
+    assert o.precision == fx.FX_PREC_FP64 and o.fp32_threshold == 1e-5
+    assert o.schedule == fx.FX_SCHED_BOUND and not o.costmodel
+    assert o.alpha == 1.0 and o.beta == 0.0
+    assert o.max_frontier_entries == 0 and o.profile == 0 and o.use_graph == 0
+    assert o.symmetry == fx.FX_SYM_AUTO and o.leaf_screen == fx.FX_LEAF_SHELL
+    d = fx.make_opts()
+    for name, _ in fx.fx_exchange_opts._fields_:
+        if name != "costmodel":
+            assert getattr(o, name) == getattr(d, name), name
+
+
+def test_costmodel_load_rejects_foreign_files(tmp_path):
+    """A missing, foreign or truncated file is refused before any device work."""
+    import ctypes as C
+    L = fx.lib()
+    h = C.c_void_p()
+    missing = tmp_path / "none.fxmlp"
+    assert L.fx_costmodel_load(os.fsencode(str(missing)), C.byref(h)) == 1
+    bad = tmp_path / "bad.fxmlp"
+    bad.write_bytes(b"FXMLP001" + b"\x00" * 12)
+    assert L.fx_costmodel_load(os.fsencode(str(bad)), C.byref(h)) == 1
+    assert not h.value
