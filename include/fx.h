@@ -229,6 +229,24 @@ fx_status fx_exchange_batched(const fx_tree* const* trees, const double* const* 
 fx_status fx_exchange_multi(const fx_tree* tree, const double* const* P, double* const* K, int32_t ndens,
                             double tau, const fx_exchange_opts* opts, fx_stats* stats, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, serving loops with a fixed memory budget): fx_exchange_ex with
+ * every work buffer taken from a device array of the library of
+ * fx_noalloc_scratch_bytes() bytes (256 MiB) instead of being allocated;
+ * the call allocates nothing (no hipMalloc, no pool allocation).  The
+ * traversal capacities are the largest that fit in the array, and an
+ * over-large K row block is split as in fx_exchange_ex when stats is given
+ * (asynchronous with stats NULL: NaN K if a level does not fit).  Returns
+ * FX_ERR_OOM before any work is enqueued when the system's fixed buffers
+ * (norm tables, unit lists, the K accumulator when beta != 0) exceed the
+ * array, and FX_ERR_INVALID_ARG for opts.use_graph or opts.profile.  Every
+ * call on a GPU shares that GPU's array (it keeps the last call's contents;
+ * what must start at zero is cleared by each call): calls that overlap on
+ * one GPU, on any streams, race and must be serialised by the caller. */
+fx_status fx_exchange_noalloc(const fx_tree* tree, const double* P, double tau, double* K,
+                              const fx_exchange_opts* opts, fx_stats* stats, void* stream);
+size_t fx_noalloc_scratch_bytes(void);
+
 /* Number of basis functions. */
 int32_t fx_nbf(const fx_tree* tree);
 /* Number of shells. */

@@ -29,7 +29,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 
 
 def _sources():
-    srcs = [os.path.join(CSRC, f) for f in ("fx_kernels.hip", "fx_host.cpp", "fx_exec.cpp", "fx_costmodel.hip")
+    srcs = [os.path.join(CSRC, f) for f in ("fx_kernels.hip", "fx_host.cpp", "fx_exec.cpp", "fx_noalloc.cpp", "fx_costmodel.hip")
             if os.path.exists(os.path.join(CSRC, f))]
     srcs += sorted(os.path.join(GEN, f) for f in os.listdir(GEN) if f.endswith(".hip"))
     return srcs

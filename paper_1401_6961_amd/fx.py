@@ -81,7 +81,8 @@ class fx_stats(ctypes.Structure):
                 "class_prec_quartets": np.array(self.class_prec_quartets, dtype=np.int64).reshape(81, 2)}
 
 
-EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_opts_init", "fx_exchange_batched", "fx_exchange_multi", "fx_nbf",
+EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_opts_init", "fx_exchange_noalloc",
+            "fx_noalloc_scratch_bytes", "fx_exchange_batched", "fx_exchange_multi", "fx_nbf",
             "fx_nshell",
             "fx_tree_perm", "fx_tree_levels", "fx_tree_schwarz", "fx_tree_free", "fx_set_allocator",
             "fx_status_string", "fx_last_error_message", "fx_plan_tree", "fx_hilbert_key3",
@@ -110,6 +111,10 @@ def lib():
                                       ctypes.POINTER(fx_exchange_opts), ctypes.POINTER(fx_stats), vp]
     L.fx_exchange_multi.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl,
                                     ctypes.POINTER(fx_exchange_opts), ctypes.POINTER(fx_stats), vp]
+    L.fx_exchange_noalloc.argtypes = [vp, vp, dbl, vp, ctypes.POINTER(fx_exchange_opts), ctypes.POINTER(fx_stats), vp]
+    L.fx_exchange_noalloc.restype = ctypes.c_int
+    L.fx_noalloc_scratch_bytes.argtypes = []
+    L.fx_noalloc_scratch_bytes.restype = ctypes.c_size_t
     L.fx_exchange_opts_init.argtypes = [ctypes.POINTER(fx_exchange_opts)]
     L.fx_exchange_opts_init.restype = None
     for f in ("fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_batched", "fx_exchange_multi", "fx_tree_perm",
@@ -306,6 +311,19 @@ def fx_exchange_ex(tree: Tree, P, tau, K, opts=None, stream=None, stats=True):
     _check(lib().fx_exchange_ex(tree.handle, ctypes.c_void_p(P.data_ptr()), float(tau),
                                 ctypes.c_void_p(K.data_ptr()), ctypes.byref(o),
                                 ctypes.byref(st) if st is not None else None, _stream_ptr(stream)))
+    return K, (st.as_dict() if st is not None else None)
+
+
+def fx_exchange_noalloc(tree: Tree, P, tau, K, opts=None, stream=None, stats=True):
+    """fx_exchange_ex working in the library's scratch array (allocates nothing)."""
+    n = tree.nbf
+    _check_matrix(P, n, "P")
+    _check_matrix(K, n, "K")
+    st = fx_stats() if stats else None
+    o = opts if opts is not None else make_opts()
+    _check(lib().fx_exchange_noalloc(tree.handle, ctypes.c_void_p(P.data_ptr()), float(tau),
+                                     ctypes.c_void_p(K.data_ptr()), ctypes.byref(o),
+                                     ctypes.byref(st) if st is not None else None, _stream_ptr(stream)))
     return K, (st.as_dict() if st is not None else None)
 
 
