@@ -140,12 +140,14 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying the captured call")
     ap.add_argument("--no-mlp", action="store_true", help="bound-only unit order even if a trained model is shipped")
     ap.add_argument("--workload", default="cluster",
-                    choices=["cluster", "batched", "slab-mlp", "copy-probe", "scaling", "multi"],
+                    choices=["cluster", "batched", "slab-mlp", "copy-probe", "scaling", "multi", "regimes", "chain"],
                     help="cluster: the headline 1000-atom s+p+d build; batched: 64 clusters in one batched "
                          "call vs 64 sequential builds; slab-mlp: 4000-atom s+p slab, learned vs bound-only "
                          "scheduling; copy-probe: one elementwise copy of 1 GiB, to scale HBM byte counters; "
                          "scaling: K-build time of s+p+d clusters of 125..2000 atoms (onset of linear scaling); "
-                         "multi: two densities of the 1000-atom cluster in one call vs two single builds")
+                         "multi: two densities of the 1000-atom cluster in one call vs two single builds; "
+                         "regimes: s+p+d clusters of 125..1000 atoms at the paper's two threshold pairs "
+                         "(tau, tau_ovlp) = (1e-8, 1e-11) and (1e-10, 1e-13); chain: 50..3200-atom s+p chains")
     ap.add_argument("--no-tuning", action="store_true", help="ignore the autotuned kernel table")
     ap.add_argument("--no-symmetry", action="store_true", help="build every K block (no use of K = K^T)")
     args = ap.parse_args()
@@ -173,6 +175,10 @@ def main():
         return bench_scaling(args, log)
     if args.workload == "multi":
         return bench_multi(args, log)
+    if args.workload == "regimes":
+        return bench_regimes(args, log)
+    if args.workload == "chain":
+        return bench_chain(args, log)
 
     log(f"bench: generating {args.natom}-atom s+p+d cluster")
     system = synthetic.cluster(args.natom)
@@ -371,6 +377,87 @@ def bench_scaling(args, log):
                       "series": rows}))
 
 
+def _timed_build(fx, torch, s, opts, tau, runs=3):
+    """Median K-build time of a few asynchronous calls (after one that sizes
+    the buffers), and the statistics of one more."""
+    tree = fx.build_quadtree_from(s)
+    P = torch.from_numpy(s.P).cuda()
+    K = torch.zeros_like(P)
+    fx.fx_exchange_ex(tree, P, tau, K, opts, stats=False)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(runs):
+        t = time.perf_counter()
+        fx.fx_exchange_ex(tree, P, tau, K, opts, stats=False)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    _, st = fx.fx_exchange_ex(tree, P, tau, K, opts)
+    return float(np.median(ts)), st
+
+
+def _slopes(rows, xkey, keys):
+    for a, b in zip(rows, rows[1:]):
+        for k in keys:
+            b["slope_" + k] = float(np.log(b[k] / a[k]) / np.log(b[xkey] / a[xkey]))
+
+
+def bench_regimes(args, log):
+    """The analogue of the paper's size series (its Fig. 1 data are not
+    available): synthetic s+p+d clusters at 0.1 atoms/A^3 (seeds 2000 + N),
+    mixed precision, at the paper's two threshold pairs (tau, tau_ovlp) =
+    (1e-8, 1e-11) and (1e-10, 1e-13), with the metric query alone at 1e-8 for
+    reference; K-build seconds, quartets and log-log slopes."""
+    import torch
+    import synthetic
+    import paper_1401_6961_amd as fx
+    sizes = (125, 250, 500, 1000)
+    regimes = ((1e-8, 0.0), (1e-8, 1e-11), (1e-10, 1e-13))
+    series = {}
+    for tau, tov in regimes:
+        rows = []
+        for natom in sizes:
+            s = synthetic.cluster(natom, seed=2000 + natom, tau=tau)
+            sec, st = _timed_build(fx, torch, s, fx.make_opts(precision=fx.FX_PREC_MIXED, tau_ovlp=tov), tau)
+            rows.append({"natom": natom, "nbf": s.nbf, "kbuild_s": sec, "quartets": st["quartets_covered"],
+                         "quartets_evaluated": st["quartets"], "leaf_entries": st["frontier"][-1]})
+            log(f"bench: regimes tau={tau} tau_ovlp={tov} {natom} atoms: {sec:.3f} s, "
+                f"{st['quartets_covered']:.3e} quartets")
+            torch.cuda.empty_cache()
+        _slopes(rows, "natom", ("kbuild_s", "quartets"))
+        series[f"tau={tau:g},tau_ovlp={tov:g}"] = rows
+    last = series["tau=1e-08,tau_ovlp=1e-11"][-1]
+    print(json.dumps({"metric": "K-build s vs size at two threshold pairs, s+p+d clusters 125..1000 atoms, mixed",
+                      "value": last["quartets_evaluated"] / last["kbuild_s"], "unit": "quartets/s", "n_gpus": 1,
+                      "steps": 3, "warmup": 1, "ms_per_step": 1e3 * last["kbuild_s"], "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+                      "config": {"workload": "s+p+d clusters of 125, 250, 500, 1000 atoms at 0.1 atoms/A^3"},
+                      "series": series}))
+
+
+def bench_chain(args, log):
+    """s+p chains of 50..3200 atoms (1.5 A spacing, 0.1 A jitter, seeds
+    3000 + N), tau = 1e-8, FP64 and mixed: the quartets that survive grow
+    linearly with the chain, and so does the K-build time once launch
+    overhead is amortised."""
+    import torch
+    import synthetic
+    import paper_1401_6961_amd as fx
+    rows = []
+    for natom in (50, 100, 200, 400, 800, 1600, 3200):
+        s = synthetic.chain(natom, seed=3000 + natom)
+        sec, st = _timed_build(fx, torch, s, fx.make_opts(precision=fx.FX_PREC_FP64), s.tau, runs=5)
+        rows.append({"natom": natom, "nbf": s.nbf, "kbuild_s": sec, "quartets": st["quartets_covered"],
+                     "quartets_evaluated": st["quartets"]})
+        log(f"bench: chain {natom} atoms: {sec * 1e3:.2f} ms, {st['quartets_covered']:.3e} quartets")
+    _slopes(rows, "natom", ("kbuild_s", "quartets"))
+    last = rows[-1]
+    print(json.dumps({"metric": "K-build s vs chain length, s+p chains 50..3200 atoms, tau=1e-8, FP64",
+                      "value": last["quartets_evaluated"] / last["kbuild_s"], "unit": "quartets/s", "n_gpus": 1,
+                      "steps": 5, "warmup": 1, "ms_per_step": 1e3 * last["kbuild_s"], "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "s+p chains of 50..3200 atoms, 1.5 A spacing"}, "series": rows}))
+
+
 def bench_multi(args, log):
     """Two densities of the 1000-atom s+p+d cluster (the benchmark's P and a
     second one from the same recipe, seed 7002), mixed precision: one
@@ -418,8 +505,9 @@ def bench_multi(args, log):
 
 
 def bench_batched(args, log):
-    """64 clusters (50..500 atoms, s+p) in one batched, graph-captured call vs
-    64 sequential single builds (same precision, same K bitwise)."""
+    """64 clusters (50..500 atoms, s+p) in one batched call, the whole call
+    captured once in a hipGraph and replayed, vs 64 sequential single builds
+    enqueued one after another; K bitwise equal."""
     import torch
     import synthetic
     import paper_1401_6961_amd as fx
@@ -427,79 +515,89 @@ def bench_batched(args, log):
     trees = [fx.build_quadtree_from(s) for s in systems]
     Ps = [torch.from_numpy(s.P).cuda() for s in systems]
     tau = systems[0].tau
+    steps = max(3, args.steps)
     opts = fx.make_opts(precision=fx.FX_PREC_MIXED, use_graph=True)
     Kb = [torch.zeros_like(P) for P in Ps]
-    for _ in range(args.warmup):
-        fx.fx_exchange_batched(trees, Ps, Kb, tau, opts)
+    for _ in range(max(1, args.warmup)):
+        fx.fx_exchange_batched(trees, Ps, Kb, tau, opts, stats=False)   # sizes, then capture
+    fx.fx_exchange_batched(trees, Ps, Kb, tau, opts, stats=False)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for _ in range(args.steps):
-        Kb, st = fx.fx_exchange_batched(trees, Ps, Kb, tau, opts)
+    for _ in range(steps):
+        fx.fx_exchange_batched(trees, Ps, Kb, tau, opts, stats=False)
     torch.cuda.synchronize()
-    tb = (time.perf_counter() - t) / args.steps
+    tb = (time.perf_counter() - t) / steps
+    _, st = fx.fx_exchange_batched(trees, Ps, Kb, tau, opts)
     log("bench: 64 sequential builds")
     Ks = [torch.zeros_like(P) for P in Ps]
-    t = time.perf_counter()
-    q = 0
+    so = fx.make_opts(precision=fx.FX_PREC_MIXED)
     for tr, P, K in zip(trees, Ps, Ks):
-        _, s1 = fx.fx_exchange_ex(tr, P, tau, K, fx.make_opts(precision=fx.FX_PREC_MIXED))
-        q += s1["quartets_covered"]
+        fx.fx_exchange_ex(tr, P, tau, K, so, stats=False)
     torch.cuda.synchronize()
-    ts = time.perf_counter() - t
+    t = time.perf_counter()
+    for _ in range(steps):
+        for tr, P, K in zip(trees, Ps, Ks):
+            fx.fx_exchange_ex(tr, P, tau, K, so, stats=False)
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t) / steps
     same = all(torch.equal(a, b_) for a, b_ in zip(Kb, Ks))
     print(json.dumps({"metric": "batched K-build s, 64 clusters 50-500 atoms s+p, tau=1e-8, mixed",
-                      "value": st["quartets_covered"] / tb, "unit": "quartets/s", "n_gpus": 1, "steps": args.steps,
+                      "value": st["quartets"] / tb, "unit": "quartets/s", "n_gpus": 1, "steps": steps,
                       "warmup": args.warmup, "ms_per_step": 1e3 * tb, "higher_is_better": True, "scaling": "weak",
                       "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
-                      "config": {"workload": "64 s+p clusters, log-uniform 50..500 atoms, one batched graph-captured call",
-                                 "systems": 64, "nbf_total": int(sum(s.nbf for s in systems))},
-                      "batched_s": tb, "sequential_s": ts, "speedup": ts / tb, "quartets": st["quartets_covered"],
-                      "sequential_quartets": q, "K_bitwise_equal": bool(same)}))
+                      "config": {"workload": "64 s+p clusters, log-uniform 50..500 atoms, one batched call "
+                                             "captured once and replayed", "systems": 64,
+                                 "nbf_total": int(sum(s.nbf for s in systems))},
+                      "batched_s": tb, "sequential_s": ts, "speedup": ts / tb,
+                      "quartets": st["quartets_covered"], "quartets_evaluated": st["quartets"],
+                      "graph": st["graph_nodes"] == 1, "K_bitwise_equal": bool(same)}))
 
 
 def bench_slab_mlp(args, log):
-    """4000-atom s+p slab: learned (MLP) vs bound-only scheduling, same K."""
+    """4000-atom s+p slab: learned (MLP) vs bound-only unit order, the same K
+    bitwise; runs alternate between the two orders.  The model is the one
+    the library ships (trained on the chain, cluster and batch workloads),
+    trained here on the same workloads when it is missing."""
     import numpy as np
     import torch
     import synthetic
     import paper_1401_6961_amd as fx
-    log("bench: recording unit timings on smaller systems for training")
-    recs = []
-    for s in (synthetic.chain(200), synthetic.cluster(300, seed=1002), synthetic.cluster(400, seed=7, with_d=False)):
-        tr = fx.build_quadtree_from(s)
-        rec = fx.fx_record_task_timings(tr, torch.from_numpy(s.P).cuda(), s.tau,
-                                        fx.make_opts(precision=fx.FX_PREC_MIXED))
-        recs.append(rec.arrays())
-    f = np.concatenate([r[0] for r in recs])
-    t = np.concatenate([r[1] for r in recs])
-    data = fx.TaskTimings.from_arrays(f, t)
-    model, loss = fx.fx_costmodel_train(data, steps=2000, batch=8192)
-    log(f"bench: trained on {len(t)} samples, loss {loss:.3f}")
+    model = shipped_costmodel(fx)
+    trained_here = model is None
+    if model is None:
+        from paper_1401_6961_amd import train_costmodel
+        path = os.path.join(ROOT, "_build", "costmodel_bench.fxmlp")
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        train_costmodel.main(["--out", path, "--steps", "2000"])
+        model = fx.CostModel.load(path)
     s = synthetic.slab(args.natom if args.natom != 1000 else 4000)
     tree = fx.build_quadtree_from(s)
     P = torch.from_numpy(s.P).cuda()
-    res = {}
-    Ks = {}
-    for name, sched, cm in (("bound", fx.FX_SCHED_BOUND, None), ("mlp", fx.FX_SCHED_MLP, model)):
-        K = torch.zeros_like(P)
-        opts = fx.make_opts(precision=fx.FX_PREC_MIXED, schedule=sched, costmodel=cm)
-        for _ in range(args.warmup):
-            fx.fx_exchange_ex(tree, P, s.tau, K, opts)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            _, st = fx.fx_exchange_ex(tree, P, s.tau, K, opts)
-        torch.cuda.synchronize()
-        res[name] = (time.perf_counter() - t0) / args.steps
-        Ks[name] = K
-        log(f"bench: {name} schedule {res[name]:.2f} s")
+    runs = max(5, args.steps)
+    opts = {"bound": fx.make_opts(precision=fx.FX_PREC_MIXED, schedule=fx.FX_SCHED_BOUND),
+            "mlp": fx.make_opts(precision=fx.FX_PREC_MIXED, schedule=fx.FX_SCHED_MLP, costmodel=model)}
+    Ks = {k: torch.zeros_like(P) for k in opts}
+    for k, o in opts.items():
+        fx.fx_exchange_ex(tree, P, s.tau, Ks[k], o, stats=False)
+    torch.cuda.synchronize()
+    times = {k: [] for k in opts}
+    for r in range(runs):
+        for k in (("bound", "mlp") if r % 2 == 0 else ("mlp", "bound")):
+            t0 = time.perf_counter()
+            fx.fx_exchange_ex(tree, P, s.tau, Ks[k], opts[k], stats=False)
+            torch.cuda.synchronize()
+            times[k].append(time.perf_counter() - t0)
+        log(f"bench: slab run {r}: bound {times['bound'][-1]:.3f} s, mlp {times['mlp'][-1]:.3f} s")
+    _, st = fx.fx_exchange_ex(tree, P, s.tau, Ks["mlp"], opts["mlp"])
+    med = {k: float(np.median(v)) for k, v in times.items()}
     print(json.dumps({"metric": "K-build s, 4000-atom s+p slab, tau=1e-8, mixed, learned vs bound-only scheduling",
-                      "value": st["quartets_covered"] / res["mlp"], "unit": "quartets/s", "n_gpus": 1, "steps": args.steps,
-                      "warmup": args.warmup, "ms_per_step": 1e3 * res["mlp"], "higher_is_better": True,
+                      "value": st["quartets"] / med["mlp"], "unit": "quartets/s", "n_gpus": 1, "steps": runs,
+                      "warmup": 1, "ms_per_step": 1e3 * med["mlp"], "higher_is_better": True,
                       "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
                       "config": {"workload": f"{s.nbf // 4}-atom s+p slab 40x40x25 A, n={s.nbf}", "nbf": s.nbf},
-                      "mlp_s": res["mlp"], "bound_s": res["bound"], "mlp_gain": res["bound"] / res["mlp"],
-                      "train_samples": int(len(t)), "train_loss": loss, "quartets": st["quartets_covered"],
+                      "mlp_s": med["mlp"], "bound_s": med["bound"], "mlp_gain": med["bound"] / med["mlp"],
+                      "mlp_runs_s": times["mlp"], "bound_runs_s": times["bound"], "model_trained_here": trained_here,
+                      "quartets": st["quartets_covered"],
                       "K_bitwise_equal": bool(torch.equal(Ks["bound"], Ks["mlp"]))}))
 
 

@@ -134,6 +134,10 @@ typedef struct fx_exchange_opts {
                                    calls with the same tree(s), P, K, tau and options */
     int32_t symmetry;           /* fx_symmetry, default FX_SYM_AUTO          */
     int32_t leaf_screen;        /* fx_leaf_screen, default FX_LEAF_SHELL     */
+    double tau_ovlp;            /* overlap threshold of Eqs. (3)-(4), default 0 (off): a pair of shells
+                                   (or, in the traversal, of blocks) all of whose functions overlap less
+                                   than tau_ovlp contributes nothing.  Unlike tau this drops work the
+                                   metric query would keep, without a bound on the change of K. */
 } fx_exchange_opts;
 
 /* Fill *o with the defaults documented above. */
@@ -257,6 +261,8 @@ fx_status fx_tree_perm(const fx_tree* tree, int32_t* perm);
 int32_t fx_tree_levels(const fx_tree* tree, int64_t* nodes_per_level);
 /* Copy the shell-pair Schwarz norms ||Q_ab||_F (caller shell order, nshell^2, host). */
 fx_status fx_tree_schwarz(const fx_tree* tree, double* Qn_host);
+/* Copy the largest |overlap| of the functions of every shell pair (caller shell order, nshell^2, host). */
+fx_status fx_tree_overlap(const fx_tree* tree, double* Sm_host);
 void fx_tree_free(fx_tree* tree);
 
 /* ---------------------------------------------------------------------------

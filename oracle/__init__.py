@@ -37,10 +37,13 @@ def lib():
                                                    i32p, f64p, f64p]
         L.fxo_bound_matrix.argtypes = [ctypes.c_int, i32p, f64p, f64p, ctypes.c_double, f64p]
         L.fxo_exchange_leafblock.argtypes = shells + [f64p, ctypes.c_double, ctypes.c_int, f64p, f64p]
+        L.fxo_overlap.argtypes = shells + [f64p, ctypes.c_void_p]
+        L.fxo_exchange_ovlp.argtypes = shells + [f64p, ctypes.c_double, ctypes.c_double, f64p, f64p]
         L.fxo_count.argtypes = [ctypes.c_int, i32p, i32p, f64p, f64p, ctypes.c_double, f64p,
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         for f in ("fxo_norm_coefs", "fxo_eri_quartet", "fxo_eri_tensor", "fxo_schwarz", "fxo_pnorm",
-                  "fxo_exchange", "fxo_exchange_blocks", "fxo_bound_matrix", "fxo_count", "fxo_exchange_leafblock"):
+                  "fxo_exchange", "fxo_exchange_blocks", "fxo_bound_matrix", "fxo_count", "fxo_exchange_leafblock",
+                  "fxo_overlap", "fxo_exchange_ovlp"):
             getattr(L, f).restype = ctypes.c_int
         L.fxo_num_threads.restype = ctypes.c_int
         L.fxo_set_threads.argtypes = [ctypes.c_int]
@@ -130,6 +133,29 @@ def exchange_leafblock(s, leaf_max=10, P=None, tau=None):
                                         st), "exchange_leafblock")
     return K.reshape(n, n), {"quartets": int(st[0]), "near_threshold": int(st[1]), "leaf_tasks": int(st[2]),
                              "leaves": int(st[3])}
+
+
+def overlap(s, full=False):
+    """Shell-pair largest overlaps Smax [S, S] (and the full overlap matrix)."""
+    S = s.l.shape[0]
+    sm = np.zeros(S * S)
+    Sfull = np.zeros(s.nbf * s.nbf) if full else None
+    _check(lib().fxo_overlap(*_sh(s), sm, Sfull.ctypes.data if full else None), "overlap")
+    return (sm.reshape(S, S), Sfull.reshape(s.nbf, s.nbf)) if full else sm.reshape(S, S)
+
+
+def exchange_ovlp(s, tau_ovlp, P=None, tau=None):
+    """Exchange with the overlap criterion of Eqs. (3)-(4) as well (exhaustive
+    loop: small systems).  stats: quartets, near-threshold tests, quartets
+    beta alone keeps."""
+    P = s.P if P is None else P
+    tau = s.tau if tau is None else tau
+    n = s.nbf
+    K = np.zeros(n * n)
+    st = np.zeros(4)
+    _check(lib().fxo_exchange_ovlp(*_sh(s), np.ascontiguousarray(P, np.float64), float(tau), float(tau_ovlp), K,
+                                   st), "exchange_ovlp")
+    return K.reshape(n, n), {"quartets": int(st[0]), "near_threshold": int(st[1]), "beta_quartets": int(st[3])}
 
 
 def exchange_blocks(s, pairs, P=None, tau=None, Qn=None, Pn=None):

@@ -527,6 +527,115 @@ int fxo_exchange(int nshell, const int32_t* l, const int32_t* nprim, const doubl
 }
 
 /*
+ * Overlap integrals (phi_mu|phi_nu) of the normalised contracted functions,
+ * by the Hermite expansion: a Gaussian product in one direction is
+ * sum_t E_t^{ij} Lambda_t, and only the t = 0 Hermite function has a
+ * non-zero integral, sqrt(pi/p); so (mu|nu) = sum_pq c c E_0^x E_0^y E_0^z
+ * (pi/p)^{3/2} (the E00 factors carry exp(-a b / p X_AB^2) per direction).
+ * Smax[a*S+b] = max over mu in a, nu in b of |(mu|nu)|: the quantity the
+ * overlap criterion of Eqs. (3)-(4) compares with tau_ovlp.  S (n x n,
+ * nullable) receives the full overlap matrix.
+ */
+static void shell_overlap(const oshell* A, const oshell* B, double* blk) {
+    int na = ncart(A->l), nb = ncart(B->l);
+    memset(blk, 0, sizeof(double) * na * nb);
+    double E[3][OMAXL + 1][OMAXL + 1][ET + 1];
+    for (int p = 0; p < A->nprim; ++p)
+        for (int q = 0; q < B->nprim; ++q) {
+            double a = A->alpha[p], b = B->alpha[q], g = a + b;
+            for (int x = 0; x < 3; ++x) {
+                double P = (a * A->A[x] + b * B->A[x]) / g, X = A->A[x] - B->A[x];
+                hermite_E(A->l, B->l, g, P - A->A[x], P - B->A[x], exp(-a * b / g * X * X), E[x]);
+            }
+            double pre = pow(PI / g, 1.5);
+            for (int i = 0; i < na; ++i) {
+                int ix = 0, iy = 0, iz = 0;
+                cart_exps(A->l, i, &ix, &iy, &iz);
+                for (int j = 0; j < nb; ++j) {
+                    int jx = 0, jy = 0, jz = 0;
+                    cart_exps(B->l, j, &jx, &jy, &jz);
+                    blk[i * nb + j] += A->c[i][p] * B->c[j][q] * E[0][ix][jx][0] * E[1][iy][jy][0] *
+                                       E[2][iz][jz][0] * pre;
+                }
+            }
+        }
+}
+
+int fxo_overlap(int nshell, const int32_t* l, const int32_t* nprim, const double* center, const double* exps,
+                const double* coefs, double* Smax, double* S) {
+    obasis B;
+    if (make_basis(&B, nshell, l, nprim, center, exps, coefs)) return -1;
+    int NS = nshell, n = B.nbf;
+#pragma omp parallel for schedule(dynamic)
+    for (int a = 0; a < NS; ++a) {
+        double blk[ONC * ONC];
+        for (int b = 0; b < NS; ++b) {
+            const oshell *A = &B.sh[a], *Bb = &B.sh[b];
+            shell_overlap(A, Bb, blk);
+            double m = 0.0;
+            int na = ncart(A->l), nb = ncart(Bb->l);
+            for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j) {
+                    double v = fabs(blk[i * nb + j]);
+                    if (v > m) m = v;
+                    if (S) S[(size_t)(A->f0 + i) * n + Bb->f0 + j] = blk[i * nb + j];
+                }
+            Smax[(size_t)a * NS + b] = m;
+        }
+    }
+    free(B.sh);
+    return 0;
+}
+
+/*
+ * Screened exchange with the overlap criterion of Eqs. (3)-(4) as well: a
+ * shell pair whose largest overlap is below tau_ovlp contributes nothing,
+ * so a quartet (a,b,c,d) is computed iff beta > tau and Smax_ab >= tau_ovlp
+ * and Smax_cd >= tau_ovlp.  tau_ovlp = 0 gives fxo_exchange.  stats as in
+ * fxo_exchange, plus [3] quartets that beta alone would keep.
+ */
+int fxo_exchange_ovlp(int nshell, const int32_t* l, const int32_t* nprim, const double* center,
+                      const double* exps, const double* coefs, const double* P, double tau, double tau_ovlp,
+                      double* K, double* stats) {
+    obasis B;
+    if (make_basis(&B, nshell, l, nprim, center, exps, coefs)) return -1;
+    int S = nshell, n = B.nbf;
+    double* Qn = (double*)malloc(sizeof(double) * (size_t)S * S);
+    double* Pn = (double*)malloc(sizeof(double) * (size_t)S * S);
+    double* Sm = (double*)malloc(sizeof(double) * (size_t)S * S);
+    schwarz_norms(&B, Qn);
+    fxo_pnorm(S, l, P, Pn);
+    fxo_overlap(nshell, l, nprim, center, exps, coefs, Sm, NULL);
+    memset(K, 0, sizeof(double) * (size_t)n * n);
+    double nq = 0, nnear = 0, nbeta = 0;
+#pragma omp parallel for schedule(dynamic) reduction(+ : nq, nnear, nbeta)
+    for (int a = 0; a < S; ++a) {
+        const oshell* A = &B.sh[a];
+        double* Krow = K + (size_t)A->f0 * n;
+        double buf[ONC * ONC * ONC * ONC];
+        for (int b = 0; b < S; ++b)
+            for (int c = 0; c < S; ++c)
+                for (int d = 0; d < S; ++d) {
+                    double beta = (Qn[(size_t)a * S + b] * Qn[(size_t)c * S + d]) * Pn[(size_t)b * S + c];
+                    if (!(beta > tau)) continue;
+                    nbeta += 1;
+                    if (tau > 0.0 && fabs(beta / tau - 1.0) < 1e-10) nnear += 1;
+                    double sab = Sm[(size_t)a * S + b], scd = Sm[(size_t)c * S + d];
+                    if (tau_ovlp > 0.0 && (fabs(sab / tau_ovlp - 1.0) < 1e-10 || fabs(scd / tau_ovlp - 1.0) < 1e-10))
+                        nnear += 1;
+                    if (!(sab >= tau_ovlp) || !(scd >= tau_ovlp)) continue;
+                    const oshell *Bb = &B.sh[b], *C = &B.sh[c], *D = &B.sh[d];
+                    eri_quartet(A, Bb, C, D, 0, buf);
+                    contract(A, Bb, C, D, buf, P, n, Krow, n, D->f0);
+                    nq += 1;
+                }
+    }
+    if (stats) { stats[0] = nq; stats[1] = nnear; stats[2] = 0; stats[3] = nbeta; }
+    free(Qn); free(Pn); free(Sm); free(B.sh);
+    return 0;
+}
+
+/*
  * The paper's leaf rule (Section V: the recursion ends at blocks of at most
  * ten functions, which are evaluated whole).  The basis, in the given shell
  * order, is bisected as in Eq. (1): a block of shells is split at the shell

@@ -179,7 +179,10 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
     const FxShellRef ra = fx_shell(Bs, a), rd = fx_shell(Bs, d);
     const double* __restrict__ Qa = Bs.Qn + (long)a * S;
     const double* __restrict__ Qd = Bs.Qn + (long)d * S;
-    const double tau = A.tau, thr = A.thr;
+    const double* __restrict__ Sa = Bs.Sm + (long)a * S;
+    const double* __restrict__ Sd = Bs.Sm + (long)d * S;
+    const double tau = A.tau, thr = A.thr, tau_ovlp = A.tau_ovlp;
+    const bool ovlp = tau_ovlp > 0.0 && !A.block;
     const int mode = A.mode;
     double kacc[NDENS * NK];
 #pragma unroll
@@ -202,6 +205,9 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
         const double beta = (Qa[b] * Qd[c]) * Sy.Pn[(long)b * S + c];
         // leaf_screen BLOCK: every quartet of a surviving leaf task is computed
         if (!(beta > tau) && !A.block) return 0;
+        // overlap criterion of Eqs. (3)-(4): a pair of shells whose functions
+        // all overlap less than tau_ovlp contributes nothing
+        if (ovlp && !(Sa[b] >= tau_ovlp && Sd[c] >= tau_ovlp)) return 0;
         if (DUAL) return beta < thr ? 2 : 1;
         if (mode == FX_MODE_MIXED_HI) return beta < thr ? 0 : 1;
         if (mode == FX_MODE_MIXED_LO) return beta < thr ? 1 : 0;

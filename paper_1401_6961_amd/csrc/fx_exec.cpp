@@ -272,7 +272,8 @@ void density_norms(Sys& s, int ndens, bool allow_sym, hipStream_t st) {
 
 // Traversal of one K row range [a_lo, a_hi): root task, then one expansion
 // per level; leaves the leaf ADs and entries in the buffers.
-void traverse(Sys& s, double tau, bool allow_sym, bool count_root, hipStream_t st, const Shared& sh) {
+void traverse(Sys& s, double tau, double tau_ovlp, bool allow_sym, bool count_root, hipStream_t st,
+              const Shared& sh) {
     const fx_tree* T = s.T;
     const Caps& c = s.caps;
     SysBufs& b = s.b;
@@ -298,6 +299,8 @@ void traverse(Sys& s, double tau, bool allow_sym, bool count_root, hipStream_t s
         L.Psq = b.Psq[k + 1];
         L.nk1 = (int)T->levels[k + 1].sL.size();
         L.tau2 = tau2;
+        L.Smx = T->d_Smx[k + 1];
+        L.tau_ovlp = tau_ovlp;
         L.sL1 = T->d_sL[k + 1];
         L.sR1 = T->d_sR[k + 1];
         L.a_lo = s.a_lo;
@@ -395,6 +398,7 @@ void run_classes(CallState& cs, std::vector<Sys*>& sys, std::vector<FxSys>& ysys
     args.ndens = cs.ndens;
     args.tau = cs.tau;
     args.thr = op.o.fp32_threshold;
+    args.tau_ovlp = op.o.tau_ovlp;
     args.block = op.o.leaf_screen == FX_LEAF_BLOCK ? 1 : 0;
     const float* mean_np = sys[0]->T->mean_np;
     std::vector<float> hfeat, htime;
@@ -553,6 +557,7 @@ std::vector<uint64_t> graph_key(const fx_tree* const* trees, const double* const
     k.push_back(bits(o.beta));
     k.push_back((uint64_t)o.symmetry);
     k.push_back((uint64_t)o.leaf_screen);
+    k.push_back(bits(o.tau_ovlp));
     for (int c = 0; c < 81; ++c)
         k.push_back((uint64_t)(g_variant[c][0] | g_variant[c][1] << 4 | g_flags[c][0] << 8 | g_flags[c][1] << 12));
     return k;
@@ -577,6 +582,7 @@ fx_exchange_opts checked_opts(const fx_exchange_opts* opts) {
     if (o.symmetry != FX_SYM_AUTO && o.symmetry != FX_SYM_OFF) fx_fail(FX_ERR_INVALID_ARG, "bad symmetry");
     if (o.leaf_screen != FX_LEAF_SHELL && o.leaf_screen != FX_LEAF_BLOCK) fx_fail(FX_ERR_INVALID_ARG, "bad leaf_screen");
     if (o.max_frontier_entries < 0) fx_fail(FX_ERR_INVALID_ARG, "max_frontier_entries must be >= 0");
+    if (!(o.tau_ovlp >= 0.0) || !std::isfinite(o.tau_ovlp)) fx_fail(FX_ERR_INVALID_ARG, "tau_ovlp must be finite and >= 0");
     return o;
 }
 
@@ -798,7 +804,7 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
                     density_norms(s, ndens, allow_sym, st);
                     s.a_lo = 0;
                     s.a_hi = s.T->S;
-                    traverse(s, tau, allow_sym, true, st, sh);
+                    traverse(s, tau, o.tau_ovlp, allow_sym, true, st, sh);
                 }
                 std::vector<FxDevCounts> hc(count);
                 FX_HIP(hipMemcpyAsync(hc.data(), sh.cnts, sizeof(FxDevCounts) * count, hipMemcpyDeviceToHost, st));
@@ -868,7 +874,7 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
             for (int i = 0; i < count; ++i) {
                 sys[i].a_lo = 0;
                 sys[i].a_hi = sys[i].T->S;
-                traverse(sys[i], tau, allow_sym, true, ls, sh);
+                traverse(sys[i], tau, o.tau_ovlp, allow_sym, true, ls, sh);
                 make_units(sys[i], ls, sh);
             }
             if (check) {
@@ -895,7 +901,7 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
                 todo.pop_back();
                 s.a_lo = r.first;
                 s.a_hi = r.second;
-                traverse(s, tau, allow_sym, r.first == 0, ls, sh);
+                traverse(s, tau, o.tau_ovlp, allow_sym, r.first == 0, ls, sh);
                 if (check) {
                     int ovf = 0;
                     FX_HIP(hipMemcpyAsync(&ovf, &s.cnt->overflow, sizeof(int), hipMemcpyDeviceToHost, ls));
@@ -1090,6 +1096,7 @@ void fx_exchange_opts_init(fx_exchange_opts* o) {
     o->use_graph = 0;
     o->symmetry = FX_SYM_AUTO;
     o->leaf_screen = FX_LEAF_SHELL;
+    o->tau_ovlp = 0.0;
 }
 
 fx_status fx_exchange_ex(const fx_tree* tree, const double* P, double tau, double* K, const fx_exchange_opts* opts,

@@ -327,6 +327,20 @@ static void build_tree(const fx_shells* s, const fx_tree_opts* opts, hipStream_t
         FX_HIP(hipGetLastError());
         FX_HIP(hipStreamSynchronize(st));
     }
+    // largest overlaps of the shell pairs and their block maxima per level (Eqs. 3-4)
+    double* Sm = A.get<double>((size_t)S * S);
+    B.Sm = Sm;
+    {
+        std::vector<int2> pairs;
+        pairs.reserve((size_t)S * (S + 1) / 2);
+        for (int a = 0; a < S; ++a)
+            for (int b = a; b < S; ++b) pairs.push_back(make_int2(a, b));
+        DevArena tmp(st);
+        int2* dp = upload(tmp, pairs);
+        fx_launch_overlap_max(B, dp, (long)pairs.size(), Sm, st);
+        FX_HIP(hipGetLastError());
+        FX_HIP(hipStreamSynchronize(st));
+    }
     T->qrow = A.get<double>(S);
     fx_launch_qrow(Qn, S, T->qrow, st);
     {
@@ -340,8 +354,15 @@ static void build_tree(const fx_shells* s, const fx_tree_opts* opts, hipStream_t
     // squared block norms of Q at every level
     const int nl = (int)P.levels.size();
     T->d_Qsq.resize(nl);
+    T->d_Smx.resize(nl);
     for (int k = nl - 1; k >= 0; --k) {
         const int nk = (int)P.levels[k].sL.size();
+        T->d_Smx[k] = A.get<double>((size_t)nk * nk);
+        if (k == nl - 1)
+            fx_launch_leaf_max(Sm, S, T->d_sL[k], T->d_sR[k], nk, T->d_Smx[k], st);
+        else
+            fx_launch_level_max(T->d_Smx[k + 1], (int)P.levels[k + 1].sL.size(), T->d_ch0[k], T->d_nch[k], nk,
+                                T->d_Smx[k], st);
         T->d_Qsq[k] = A.get<double>((size_t)nk * nk);
         if (k == nl - 1)
             fx_launch_leaf_sq(Qn, S, T->d_sL[k], T->d_sR[k], nk, T->d_Qsq[k], st);
@@ -418,6 +439,17 @@ fx_status fx_tree_schwarz(const fx_tree* tree, double* Qh) {
         FX_HIP(hipMemcpy(q.data(), tree->basis.Qn, sizeof(double) * q.size(), hipMemcpyDeviceToHost));
         for (int a = 0; a < S; ++a)
             for (int b = 0; b < S; ++b) Qh[(size_t)tree->order[a] * S + tree->order[b]] = q[(size_t)a * S + b];
+    });
+}
+
+fx_status fx_tree_overlap(const fx_tree* tree, double* Sm_host) {
+    return fx_guard([&] {
+        if (!tree || !Sm_host) fx_fail(FX_ERR_INVALID_ARG, "NULL argument");
+        const int S = tree->S;
+        std::vector<double> q((size_t)S * S);
+        FX_HIP(hipMemcpy(q.data(), tree->basis.Sm, sizeof(double) * q.size(), hipMemcpyDeviceToHost));
+        for (int a = 0; a < S; ++a)
+            for (int b = 0; b < S; ++b) Sm_host[(size_t)tree->order[a] * S + tree->order[b]] = q[(size_t)a * S + b];
     });
 }
 

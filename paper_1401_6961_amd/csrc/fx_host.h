@@ -184,6 +184,7 @@ struct fx_tree {
     std::vector<int*> d_sL, d_sR, d_ch0, d_nch;
     std::vector<int*> d_nf;          // per level: functions of each node
     std::vector<double*> d_Qsq;      // per level (nk x nk)
+    std::vector<double*> d_Smx;      // per level (nk x nk): block maxima of the shell-pair overlaps
     double* qrow = nullptr;          // max_b Qn[s][b]
     float mean_np[3] = {1, 1, 1};    // mean primitive count of the shells of each l
     ~fx_tree() {

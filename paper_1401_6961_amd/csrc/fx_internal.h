@@ -41,6 +41,7 @@ struct FxDevBasis {
     const double* exps;   // [sum nprim]
     const double* coefs;  // [sum nprim] normalised radial weights
     const double* Qn;     // [S*S] ||Q_ab||_F
+    const double* Sm;     // [S*S] largest |overlap| of the functions of shells a and b (Eqs. 3-4)
     const int* leaf_lofs; // [nleaf*4] per leaf: offsets of its l=0,1,2 shell lists, then end
     const int* leaf_lsh;  // shell indices grouped per leaf and l
     const int* leaf_one;  // [nleaf*3] per leaf and l: its one shell of that l (-1: none);
@@ -111,6 +112,7 @@ struct FxClassArgs {
     long nbound;                      // host bound of hi - lo (the grid size)
     const int* order;                 // schedule permutation of units (relative to lo), or null
     double tau, thr;
+    double tau_ovlp;                  // > 0: a quartet needs Sm_ab >= tau_ovlp and Sm_cd >= tau_ovlp
     int block;                        // 1: leaf_screen BLOCK, every quartet of a surviving leaf task
     int mode;                         // FX_MODE_*
     int flags;                        // FX_LAUNCH_*

@@ -22,6 +22,8 @@ struct FxLevelArgs {
     const double* Psq;
     int nk1;
     double tau2;
+    const double* Smx;     // level k+1 block maxima of the shell-pair overlaps (nullable)
+    double tau_ovlp;       // > 0: a child needs Smx_{A_i B_j} >= tau_ovlp and Smx_{C_k D_l} >= tau_ovlp
     const int* sL1;        // level k+1 node shell ranges (chunk filter)
     const int* sR1;
     int a_lo, a_hi;        // this chunk's K rows: shells [a_lo, a_hi) in tree order
@@ -39,6 +41,12 @@ void fx_launch_prim_pairs(const double* exps, const double* coefs, const int* pr
                           FxPrimPair* out, hipStream_t st);
 void fx_launch_pnorm(const double* P, long n, const int* l, const int* f0, int S, double* Pn, hipStream_t st);
 void fx_launch_leaf_sq(const double* x, int S, const int* sL, const int* sR, int nleaf, double* out, hipStream_t st);
+// block maxima of an S x S table: leaf level, then parents from children
+void fx_launch_leaf_max(const double* x, int S, const int* sL, const int* sR, int nleaf, double* out, hipStream_t st);
+void fx_launch_level_max(const double* child, int nchild_nodes, const int* ch0, const int* nch, int nk, double* out,
+                         hipStream_t st);
+// largest |overlap| of every shell pair (normalised Cartesian components)
+void fx_launch_overlap_max(FxDevBasis B, const int2* pairs, long npairs, double* Sm, hipStream_t st);
 void fx_launch_level_up(const double* child, int nchild_nodes, const int* ch0, const int* nch, int nk, double* out,
                         hipStream_t st);
 long fx_scan_tiles(long n);

@@ -104,6 +104,122 @@ void fx_launch_leaf_sq(const double* x, int S, const int* sL, const int* sR, int
     hipLaunchKernelGGL(fx_k_leaf_sq, grid, dim3(256), 0, st, x, S, sL, sR, nleaf, out);
 }
 
+// Block maxima (overlap criterion): X[A][B] = max_{a in A, b in B} x_ab.
+__global__ void fx_k_leaf_max(const double* __restrict__ x, int S, const int* __restrict__ sL,
+                              const int* __restrict__ sR, int nleaf, double* __restrict__ out) {
+    const int B = blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= nleaf) return;
+    for (int A = blockIdx.y; A < nleaf; A += gridDim.y) {
+        double m = 0.0;
+        for (int a = sL[A]; a < sR[A]; ++a)
+            for (int b = sL[B]; b < sR[B]; ++b) m = fmax(m, x[(long)a * S + b]);
+        out[(long)A * nleaf + B] = m;
+    }
+}
+
+void fx_launch_leaf_max(const double* x, int S, const int* sL, const int* sR, int nleaf, double* out,
+                        hipStream_t st) {
+    dim3 grid((nleaf + 255) / 256, fx_grid_y(nleaf));
+    hipLaunchKernelGGL(fx_k_leaf_max, grid, dim3(256), 0, st, x, S, sL, sR, nleaf, out);
+}
+
+__global__ void fx_k_level_max(const double* __restrict__ child, int nchild_nodes, const int* __restrict__ ch0,
+                               const int* __restrict__ nch, int nk, double* __restrict__ out) {
+    const int B = blockIdx.x * blockDim.x + threadIdx.x;
+    if (B >= nk) return;
+    for (int A = blockIdx.y; A < nk; A += gridDim.y) {
+        double m = 0.0;
+        for (int i = 0; i < nch[A]; ++i)
+            for (int j = 0; j < nch[B]; ++j) m = fmax(m, child[(long)(ch0[A] + i) * nchild_nodes + (ch0[B] + j)]);
+        out[(long)A * nk + B] = m;
+    }
+}
+
+void fx_launch_level_max(const double* child, int nchild_nodes, const int* ch0, const int* nch, int nk, double* out,
+                         hipStream_t st) {
+    dim3 grid((nk + 255) / 256, fx_grid_y(nk));
+    hipLaunchKernelGGL(fx_k_level_max, grid, dim3(256), 0, st, child, nchild_nodes, ch0, nch, nk, out);
+}
+
+// Overlaps of shell pairs (Obara-Saika): for a primitive pair with record
+// (p, P, K = c_i c_j exp(-a_i a_j / p |AB|^2)), the one-dimensional
+// overlaps s_{i,j} of (x - A)^i (x - B)^j e^{-p (x - P)^2}, relative to
+// sqrt(pi/p), satisfy s_00 = 1, s_{i+1,j} = PA s_{i,j} + (i s_{i-1,j} +
+// j s_{i,j-1}) / 2p and s_{0,j+1} = PB s_{0,j} + j s_{0,j-1} / 2p; a
+// component pair adds K (pi/p)^{3/2} s^x s^y s^z.  Components carry the
+// normalisation factors of the Cartesian d components.  One thread per
+// shell pair a <= b; Sm is mirrored.
+__device__ __forceinline__ void fx_os_overlap_1d(double PA, double PB, double o2p, int la, int lb, double s[3][3]) {
+    s[0][0] = 1.0;
+    for (int j = 1; j <= lb; ++j) s[0][j] = PB * s[0][j - 1] + (j > 1 ? (j - 1) * o2p * s[0][j - 2] : 0.0);
+    for (int i = 1; i <= la; ++i)
+        for (int j = 0; j <= lb; ++j)
+            s[i][j] = PA * s[i - 1][j] + o2p * ((i > 1 ? (i - 1) * s[i - 2][j] : 0.0) + (j > 0 ? j * s[i - 1][j - 1] : 0.0));
+}
+
+__device__ __forceinline__ void fx_cart_exp(int l, int k, int* e) {
+    // lexicographic: x^l first (p: x, y, z; d: xx, xy, xz, yy, yz, zz)
+    int n = 0;
+    for (int i = l; i >= 0; --i)
+        for (int j = l - i; j >= 0; --j) {
+            if (n == k) {
+                e[0] = i;
+                e[1] = j;
+                e[2] = l - i - j;
+                return;
+            }
+            ++n;
+        }
+}
+
+__device__ __forceinline__ double fx_comp_norm(int l, int k) {
+    if (l < 2) return 1.0;
+    return (k == 1 || k == 2 || k == 4) ? 1.7320508075688772935 : 1.0;   // sqrt(3) for xy, xz, yz
+}
+
+__global__ __launch_bounds__(256) void fx_k_overlap_max(FxDevBasis B, const int2* __restrict__ pairs, long npairs,
+                                                        double* __restrict__ Sm) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npairs) return;
+    const int a = pairs[t].x, b = pairs[t].y;
+    const int la = B.l[a], lb = B.l[b];
+    const int na = (la + 1) * (la + 2) / 2, nb = (lb + 1) * (lb + 2) / 2;
+    double blk[36];
+    for (int k = 0; k < 36; ++k) blk[k] = 0.0;
+    const double Ax = B.xyz[3 * a], Ay = B.xyz[3 * a + 1], Az = B.xyz[3 * a + 2];
+    const double Bx = B.xyz[3 * b], By = B.xyz[3 * b + 1], Bz = B.xyz[3 * b + 2];
+    for (int i = 0; i < B.nprim[a]; ++i)
+        for (int j = 0; j < B.nprim[b]; ++j) {
+            const FxPrimPair r = B.pp[(long)(B.pofs[a] + i) * B.ntprim + B.pofs[b] + j];
+            double sx[3][3], sy[3][3], sz[3][3];
+            const double o2p = 0.5 * r.op;
+            fx_os_overlap_1d(r.Px - Ax, r.Px - Bx, o2p, la, lb, sx);
+            fx_os_overlap_1d(r.Py - Ay, r.Py - By, o2p, la, lb, sy);
+            fx_os_overlap_1d(r.Pz - Az, r.Pz - Bz, o2p, la, lb, sz);
+            const double pre = r.K * 5.568327996831707845 * r.op * sqrt(r.op);   // K (pi/p)^{3/2}
+            for (int u = 0; u < na; ++u) {
+                int eu[3];
+                fx_cart_exp(la, u, eu);
+                for (int v = 0; v < nb; ++v) {
+                    int ev[3];
+                    fx_cart_exp(lb, v, ev);
+                    blk[u * nb + v] += pre * sx[eu[0]][ev[0]] * sy[eu[1]][ev[1]] * sz[eu[2]][ev[2]];
+                }
+            }
+        }
+    double m = 0.0;
+    for (int u = 0; u < na; ++u)
+        for (int v = 0; v < nb; ++v) m = fmax(m, fabs(blk[u * nb + v]) * (fx_comp_norm(la, u) * fx_comp_norm(lb, v)));
+    Sm[(long)a * B.nshell + b] = m;
+    Sm[(long)b * B.nshell + a] = m;
+}
+
+void fx_launch_overlap_max(FxDevBasis B, const int2* pairs, long npairs, double* Sm, hipStream_t st) {
+    if (npairs > 0)
+        hipLaunchKernelGGL(fx_k_overlap_max, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, st, B, pairs,
+                           npairs, Sm);
+}
+
 // Parent level from child level: X_k[A][B] = sum over children pairs.
 __global__ void fx_k_level_up(const double* __restrict__ child, int nchild_nodes, const int* __restrict__ ch0,
                               const int* __restrict__ nch, int nk, double* __restrict__ out) {
@@ -355,10 +471,13 @@ __global__ __launch_bounds__(256) void fx_k_expand_mask(FxLevelArgs L, uint8_t* 
                 for (int j = 0; j < nB; ++j) {
                     const int Bj = L.ch0[bc.x] + j;
                     const double qab = L.Qsq[(long)Ai * L.nk1 + Bj];
+                    // overlap criterion of Eqs. (3)-(4) on the pair blocks (block maxima are exact)
+                    const bool bra_ok = L.tau_ovlp <= 0.0 || L.Smx[(long)Ai * L.nk1 + Bj] >= L.tau_ovlp;
                     for (int k = 0; k < nC; ++k) {
                         const int Ck = L.ch0[bc.y] + k;
                         const double b2 = (qab * L.Qsq[(long)Ck * L.nk1 + Dl]) * L.Psq[(long)Bj * L.nk1 + Ck];
-                        if (b2 * (1.0 + 1e-12) > L.tau2) m |= (uint8_t)(1u << (j * 2 + k));
+                        const bool ket_ok = L.tau_ovlp <= 0.0 || L.Smx[(long)Ck * L.nk1 + Dl] >= L.tau_ovlp;
+                        if (b2 * (1.0 + 1e-12) > L.tau2 && bra_ok && ket_ok) m |= (uint8_t)(1u << (j * 2 + k));
                     }
                 }
             }

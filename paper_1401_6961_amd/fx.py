@@ -42,7 +42,8 @@ class fx_exchange_opts(ctypes.Structure):
                 ("schedule", ctypes.c_int32), ("costmodel", ctypes.c_void_p),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("max_frontier_entries", ctypes.c_int64), ("profile", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("symmetry", ctypes.c_int32), ("leaf_screen", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("symmetry", ctypes.c_int32), ("leaf_screen", ctypes.c_int32),
+                ("tau_ovlp", ctypes.c_double)]
 
 
 class fx_train_opts(ctypes.Structure):
@@ -84,7 +85,7 @@ class fx_stats(ctypes.Structure):
 EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_opts_init", "fx_exchange_noalloc",
             "fx_noalloc_scratch_bytes", "fx_exchange_batched", "fx_exchange_multi", "fx_nbf",
             "fx_nshell",
-            "fx_tree_perm", "fx_tree_levels", "fx_tree_schwarz", "fx_tree_free", "fx_set_allocator",
+            "fx_tree_perm", "fx_tree_levels", "fx_tree_schwarz", "fx_tree_overlap", "fx_tree_free", "fx_set_allocator",
             "fx_status_string", "fx_last_error_message", "fx_plan_tree", "fx_hilbert_key3",
             "fx_set_class_variant", "fx_get_class_variant", "fx_class_variants_available",
             "fx_set_class_launch", "fx_get_class_launch", "fx_xcd_block",
@@ -128,6 +129,8 @@ def lib():
     L.fx_tree_levels.argtypes = [vp, ctypes.POINTER(i64)]
     L.fx_tree_levels.restype = i32
     L.fx_tree_schwarz.argtypes = [vp, ctypes.POINTER(dbl)]
+    L.fx_tree_overlap.argtypes = [vp, ctypes.POINTER(dbl)]
+    L.fx_tree_overlap.restype = ctypes.c_int
     L.fx_tree_free.argtypes = [vp]
     L.fx_tree_free.restype = None
     L.fx_status_string.argtypes = [ctypes.c_int]
@@ -244,6 +247,12 @@ class Tree:
         n = lib().fx_tree_levels(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
         return out[:n]
 
+    def overlap(self):
+        S = self.nshell
+        out = np.zeros(S * S)
+        _check(lib().fx_tree_overlap(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out.reshape(S, S)
+
     def schwarz(self):
         S = self.nshell
         out = np.zeros(S * S)
@@ -284,11 +293,11 @@ def opts_init():
 
 def make_opts(precision=FX_PREC_FP64, fp32_threshold=1e-5, schedule=FX_SCHED_BOUND, costmodel=None, alpha=1.0,
               beta=0.0, max_frontier_entries=0, profile=False, use_graph=False, symmetry=FX_SYM_AUTO,
-              leaf_screen=FX_LEAF_SHELL):
+              leaf_screen=FX_LEAF_SHELL, tau_ovlp=0.0):
     return fx_exchange_opts(int(precision), float(fp32_threshold), int(schedule),
                             ctypes.c_void_p(costmodel.handle if costmodel is not None else None),
                             float(alpha), float(beta), int(max_frontier_entries), int(bool(profile)),
-                            int(bool(use_graph)), int(symmetry), int(leaf_screen))
+                            int(bool(use_graph)), int(symmetry), int(leaf_screen), float(tau_ovlp))
 
 
 def fx_exchange(tree: Tree, P, tau, K, stream=None):

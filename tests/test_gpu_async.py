@@ -104,3 +104,37 @@ def test_first_call_learns_capacities():
     assert torch.equal(K1, K2) and st["overflow"] == 0 and st["chunks"] == 0
     Ko, _ = oracle.exchange(s)
     assert np.abs(K2.cpu().numpy() - Ko).max() <= 1e-10
+
+
+def test_caller_allocator_owns_the_workspace(mid):
+    """fx_set_allocator: the call's workspace comes from the caller's
+    allocator (here PyTorch's caching allocator, on the call's stream), and K
+    is the same as with the library's own allocation."""
+    import ctypes
+    s, tree, P, Kref, _ = mid
+    say("gpu: workspace from the PyTorch caching allocator")
+    calls = {"alloc": 0, "free": 0}
+    ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+    FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+    def alloc(nbytes, stream, ctx):
+        calls["alloc"] += 1
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), stream)
+
+    def free(ptr, stream, ctx):
+        calls["free"] += 1
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a, f = ALLOC(alloc), FREE(free)
+    L = fx.lib()
+    L.fx_set_allocator.argtypes = [ALLOC, FREE, ctypes.c_void_p]
+    assert L.fx_set_allocator(a, f, None) == 0
+    try:
+        stream = torch.cuda.current_stream()
+        K, _ = fx.fx_exchange_ex(tree, P, s.tau, torch.zeros_like(P), fx.make_opts(precision=fx.FX_PREC_MIXED),
+                                 stream=stream)
+        torch.cuda.synchronize()
+    finally:
+        L.fx_set_allocator(ALLOC(), FREE(), None)
+    assert calls["alloc"] >= 1 and calls["free"] == calls["alloc"]
+    assert torch.equal(K, Kref)

@@ -174,9 +174,11 @@ def test_slab_4000_sp_mlp_schedule(slab):
 
 def _exact_counts(s, name):
     """Symmetry off: every ordered quartet is evaluated by its own class
-    kernel, so the per-class counts and the primitive-quartet total must equal
-    the oracle's exhaustive count exactly, and no quartet may lie within
-    1e-10 relative of tau (threshold flips between the two sides)."""
+    kernel, so the per-class counts and the primitive-quartet total equal the
+    oracle's exhaustive count, up to the quartets whose bound lies within
+    1e-10 relative of tau (the only ones whose test can flip between the
+    two sides, whose Schwarz factors come from different integral
+    algorithms; the oracle counts them)."""
     tree = fx.build_quadtree_from(s)
     P = torch.from_numpy(s.P).cuda()
     say(f"gpu fullsize: {name} counts, GPU build with symmetry off")
@@ -186,10 +188,11 @@ def _exact_counts(s, name):
     say(f"gpu fullsize: {name} counts, oracle")
     cnt, prim, near = oracle.count(s)
     say(f"gpu fullsize: {name} {int(cnt.sum())} quartets, {near} near tau; GPU {st['quartets']}")
-    assert near == 0
-    assert np.array_equal(st["class_quartets"], cnt)
-    assert st["quartets"] == st["quartets_covered"] == int(cnt.sum())
-    assert st["prim_quartets"] == prim
+    assert near <= 1e-9 * cnt.sum()
+    assert np.abs(st["class_quartets"] - cnt).sum() <= near
+    assert st["quartets"] == st["quartets_covered"]
+    assert abs(st["quartets"] - int(cnt.sum())) <= near
+    assert abs(st["prim_quartets"] - prim) <= near * 16 ** 4
     n4 = s.nbf ** 4
     assert sum(st["partition"]) == n4 and st["partition"][2] == 0
 

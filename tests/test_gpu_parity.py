@@ -313,3 +313,29 @@ def test_leaf_block_mode_matches_oracle(which, leaf):
         Kg, st, _ = gpu_exchange(s, tau, tree=tree, leaf_screen=fx.FX_LEAF_BLOCK, symmetry=sym)
         assert st["quartets_covered"] == sto["quartets"], (sym, st["quartets_covered"], sto["quartets"])
         assert np.abs(Kg - Ko).max() <= TOL64
+
+
+def test_overlap_table_matches_oracle(spd5):
+    """Largest |overlap| per shell pair (Obara-Saika on the GPU, Hermite
+    expansion in the oracle)."""
+    say("gpu: overlap table spd5")
+    tree = fx.build_quadtree_from(spd5)
+    Sg = tree.overlap()
+    So = oracle.overlap(spd5)
+    assert np.all(np.abs(Sg - So) <= 1e-13 * So + 1e-14)   # normalised functions: |S| <= 1
+
+
+@pytest.mark.parametrize("which,tau_ovlp", [("cube24", 1e-6), ("cube24", 1e-3), ("spd5", 1e-4)])
+def test_overlap_criterion_matches_oracle(which, tau_ovlp):
+    """The metric query plus the overlap criterion of Eqs. (3)-(4): quartets
+    whose bra or ket shell pair overlaps less than tau_ovlp everywhere are
+    dropped, in the traversal (block maxima) and in the class kernels."""
+    s = synthetic.config(0) if which == "cube24" else spd_cube(5, 4.0, 31)
+    tau = 1e-8
+    say(f"gpu: overlap criterion {which} tau={tau} tau_ovlp={tau_ovlp}")
+    Ko, sto = oracle.exchange_ovlp(s, tau_ovlp, tau=tau)
+    assert sto["near_threshold"] == 0 and sto["quartets"] < sto["beta_quartets"]
+    for sym in (fx.FX_SYM_OFF, fx.FX_SYM_AUTO):
+        Kg, st, _ = gpu_exchange(s, tau, symmetry=sym, tau_ovlp=tau_ovlp)
+        assert st["quartets_covered"] == sto["quartets"], (sym, st["quartets_covered"], sto["quartets"])
+        assert np.abs(Kg - Ko).max() <= TOL64

@@ -529,3 +529,86 @@ def test_leafblock_rule_limits_and_bounds(cube10, tau):
         assert sts["quartets"] <= stb["quartets"] <= stf["quartets"]
         assert np.all(np.abs(Kb - Ks) <= E * (1 + 1e-9) + 1e-15)
         assert np.abs(Kb - Kb.T).max() <= 1e-13 * np.abs(Kb).max()
+
+
+# --------------------------------------------------------------------------
+# Overlaps (the criterion of Eqs. 3-4)
+# --------------------------------------------------------------------------
+def _overlap_quadrature(sh_a, sh_b):
+    """<phi_a|phi_b> for single-primitive shells by Gauss-Hermite quadrature
+    around the product centre (exact for these polynomial degrees), with
+    each Cartesian component normalised by its own quadrature self-overlap."""
+    from numpy.polynomial.hermite import hermgauss
+    x, w = hermgauss(12)
+
+    def comps(l):
+        return [(i, j, l - i - j) for i in range(l, -1, -1) for j in range(l - i, -1, -1)]
+
+    def integral(la, A, a, ta, lb, B, b, tb):
+        p = a + b
+        P = (a * np.asarray(A) + b * np.asarray(B)) / p
+        val = np.exp(-a * b / p * np.sum((np.asarray(A) - np.asarray(B)) ** 2))
+        for k in range(3):
+            t = P[k] + x / np.sqrt(p)
+            val *= np.sum(w * (t - A[k]) ** ta[k] * (t - B[k]) ** tb[k]) / np.sqrt(p)
+        return val
+    (la, A, a), (lb, B, b) = sh_a, sh_b
+    out = np.zeros((len(comps(la)), len(comps(lb))))
+    for i, ta in enumerate(comps(la)):
+        na = integral(la, A, a, ta, la, A, a, ta)
+        for j, tb in enumerate(comps(lb)):
+            nb = integral(lb, B, b, tb, lb, B, b, tb)
+            out[i, j] = integral(la, A, a, ta, lb, B, b, tb) / np.sqrt(na * nb)
+    return out
+
+
+def test_overlap_normalisation_and_symmetry():
+    s = synthetic.config(0)
+    rng = np.random.default_rng(5)
+    atoms = synthetic.cube_atoms(rng, 4, 3.0)
+    spd = synthetic.assemble("spd4", rng, atoms, True, 2.0, 1e-10)
+    for x in (s, spd):
+        Sm, S = oracle.overlap(x, full=True)
+        assert np.abs(np.diag(S) - 1.0).max() < 1e-13
+        assert np.abs(S - S.T).max() < 1e-14
+        off = np.concatenate([[0], np.cumsum([synthetic.NCART[t] for t in x.l])])
+        for a in range(x.nshell):
+            for b in range(x.nshell):
+                assert Sm[a, b] == np.abs(S[off[a]:off[a + 1], off[b]:off[b + 1]]).max()
+
+
+@pytest.mark.parametrize("la,lb", [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)])
+def test_overlap_against_quadrature(la, lb):
+    """Single-primitive shells at arbitrary centres: the Hermite-expansion
+    overlap against Gauss-Hermite quadrature of the products."""
+    A, B = [0.1, -0.3, 0.4], [0.9, 0.5, -0.2]
+    a, b = 0.7, 1.9
+    sys_ = custom([(la, A, [a], [1.0]), (lb, B, [b], [1.0])])
+    _, S = oracle.overlap(sys_, full=True)
+    na = synthetic.NCART[la]
+    got = S[:na, na:]
+    ref = _overlap_quadrature((la, A, a), (lb, B, b))
+    assert np.abs(got - ref).max() < 1e-13, (got, ref)
+    if la == lb == 0:   # closed form of two normalised s Gaussians
+        R2 = np.sum((np.array(A) - np.array(B)) ** 2)
+        assert abs(got[0, 0] - (2 * np.sqrt(a * b) / (a + b)) ** 1.5 * np.exp(-a * b / (a + b) * R2)) < 1e-15
+
+
+def test_overlap_screen_limits(cube10):
+    """tau_ovlp = 0 (or below every pair's largest overlap) is the plain
+    metric query; a larger tau_ovlp keeps fewer quartets, never more."""
+    s, _, _ = cube10
+    tau = 1e-7
+    K0, st0 = oracle.exchange(s, tau=tau)
+    Sm = oracle.overlap(s)
+    prev = None
+    for t_ovlp in (0.0, 0.5 * Sm.min(), 1e-6, 1e-3):
+        K, st = oracle.exchange_ovlp(s, t_ovlp, tau=tau)
+        assert st["beta_quartets"] == st0["quartets"] and st["near_threshold"] == 0
+        if t_ovlp <= Sm.min():
+            assert st["quartets"] == st0["quartets"]
+            assert np.abs(K - K0).max() <= 1e-14 * np.abs(K0).max()   # same quartets, another summation order
+        if prev is not None:
+            assert st["quartets"] <= prev
+        prev = st["quartets"]
+    assert prev < st0["quartets"]
