@@ -40,6 +40,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr long kEntryMax = 0xFFFFFFFFL;   // expansion positions are 32-bit
 constexpr int kBins = 32;
+constexpr size_t kDefaultWorkspace = size_t(4) << 30;   // default workspace budget of one call
 
 // Sequential sub-allocation of one device block; a null base only measures.
 struct Carve {
@@ -104,6 +105,7 @@ struct Shared {
     unsigned long long* part = nullptr;
     FxDevCounts* cnts = nullptr;              // one per system
     FxDevRun* run = nullptr;                  // call totals and sizes seen (next call's capacities)
+    unsigned long long* rows = nullptr;       // leaf entries per leaf row (first call on a tree)
     long* partial = nullptr;
     long* total = nullptr;
     // scheduling
@@ -135,8 +137,12 @@ long ipow4(long x) {
     return (y > 0 && y < (1L << 31)) ? y * y : (1L << 62);
 }
 
-// Capacities of one system from the tree, the hint and the options.
-Caps make_caps(const fx_tree* T, long e_in, long e_leaf) {
+using Ranges = std::vector<std::pair<int, int>>;
+
+// Capacities of one system from the tree, the entry capacities and the K row
+// ranges the traversal will be run over: a range's ADs have their A node
+// among the level's nodes that meet it, and its units their a shell in it.
+Caps make_caps(const fx_tree* T, long e_in, long e_leaf, const Ranges& ranges) {
     Caps c;
     const int nl = (int)T->levels.size();
     c.e_in = std::max(1L, std::min(e_in, kEntryMax));
@@ -144,24 +150,39 @@ Caps make_caps(const fx_tree* T, long e_in, long e_leaf) {
     c.e_lvl.resize(nl);
     c.ad_lvl.resize(nl);
     for (int k = 0; k < nl; ++k) {
-        const long nk = (long)T->levels[k].sL.size();
-        c.ad_lvl[k] = nk * nk;
+        const Level& L = T->levels[k];
+        const long nk = (long)L.sL.size();
+        long na = 0;
+        for (const auto& r : ranges) {
+            // a level's nodes partition the shells in order
+            const long first = std::upper_bound(L.sR.begin(), L.sR.end(), r.first) - L.sR.begin();
+            const long last = std::lower_bound(L.sL.begin(), L.sL.end(), r.second) - L.sL.begin();
+            na = std::max(na, last - first);
+        }
+        c.ad_lvl[k] = std::max(1L, na) * nk;
         c.e_lvl[k] = std::min(k == nl - 1 ? c.e_leaf : c.e_in, ipow4(nk));
         c.ad_max = std::max(c.ad_max, c.ad_lvl[k]);
     }
     c.e_in = std::max(1L, std::min(c.e_in, nl > 1 ? *std::max_element(c.e_lvl.begin(), c.e_lvl.end() - 1) : 1L));
     c.e_leaf = std::max(1L, c.e_lvl[nl - 1]);
     c.items = c.ad_lvl[nl - 1];
-    long nsh[3] = {0, 0, 0};
-    for (int x : T->l) nsh[x] += 1;
+    std::vector<long> pre[3];
+    for (int x = 0; x < 3; ++x) pre[x].assign(T->S + 1, 0);
+    for (int i = 0; i < T->S; ++i)
+        for (int x = 0; x < 3; ++x) pre[x][i + 1] = pre[x][i] + (T->l[i] == x);
+    long nra[3] = {0, 0, 0};
+    for (const auto& r : ranges)
+        for (int x = 0; x < 3; ++x) nra[x] = std::max(nra[x], pre[x][r.second] - pre[x][r.first]);
     c.units = 0;
     for (int la = 0; la < 3; ++la)
         for (int ld = 0; ld < 3; ++ld) {
-            c.ucap[la * 3 + ld] = nsh[la] * nsh[ld];
+            c.ucap[la * 3 + ld] = nra[la] * pre[ld][T->S];
             c.units += c.ucap[la * 3 + ld];
         }
     return c;
 }
+
+Ranges whole_rows(const fx_tree* T) { return Ranges{{0, T->S}}; }
 
 long scan_tiles_max(const Caps& c) {
     long m = std::max({fx_scan_tiles(4 * c.e_in), fx_scan_tiles(4 * c.ad_max), fx_scan_tiles(9 * c.items)});
@@ -209,6 +230,9 @@ void carve_shared(Carve& cv, Shared& sh, std::vector<Sys>& sys, const Opts& op) 
     sh.part = sh.counters ? sh.counters + 81 * 2 * 3 : nullptr;
     sh.cnts = cv.take<FxDevCounts>(count);
     sh.run = cv.take<FxDevRun>(1);
+    size_t nleaf = 1;
+    for (auto& s : sys) nleaf = std::max(nleaf, s.T->levels.back().sL.size());
+    sh.rows = cv.take<unsigned long long>(nleaf);
     long tiles = 1, umax = 0;
     for (auto& s : sys) tiles = std::max(tiles, scan_tiles_max(s.caps));
     for (int k = 0; k < 9; ++k) {
@@ -603,16 +627,34 @@ int split_rows(const fx_tree* T, int lo, int hi) {
     return best;
 }
 
-// nchunks K row ranges of about equal leaf counts, at leaf boundaries
-std::vector<std::pair<int, int>> row_ranges(const fx_tree* T, int nchunks) {
+// nchunks K row ranges at leaf boundaries: of about equal leaf entries when
+// the tree has counted them, else of about equal leaf counts
+Ranges row_ranges(const fx_tree* T, int nchunks) {
     const Level& leaf = T->levels.back();
     const int nleaf = (int)leaf.sL.size();
     nchunks = std::max(1, std::min(nchunks, nleaf));
-    std::vector<std::pair<int, int>> r;
-    for (int c = 0; c < nchunks; ++c) {
-        const int l0 = (int)((long)c * nleaf / nchunks), l1 = (int)((long)(c + 1) * nleaf / nchunks);
-        r.push_back({leaf.sL[l0], l1 < nleaf ? leaf.sL[l1] : T->S});
+    std::vector<int> cut(nchunks + 1, nleaf);
+    cut[0] = 0;
+    const std::vector<long>& rows = T->hint.leaf_rows;
+    long total = 0;
+    if ((int)rows.size() == nleaf)
+        for (long x : rows) total += x;
+    if (total > 0) {
+        // cut c at the first leaf whose running sum reaches c/nchunks of the total,
+        // keeping at least one leaf per range
+        long run = 0;
+        int c = 1;
+        for (int i = 0; i < nleaf && c < nchunks; ++i) {
+            run += rows[i];
+            while (c < nchunks && (double)run >= (double)total * c / nchunks) cut[c++] = i + 1;
+        }
+        for (int k = 1; k < nchunks; ++k) cut[k] = std::max(cut[k], cut[k - 1] + 1);
+        for (int k = nchunks - 1; k >= 1; --k) cut[k] = std::min(cut[k], cut[k + 1] - 1);
+    } else {
+        for (int k = 1; k < nchunks; ++k) cut[k] = (int)((long)k * nleaf / nchunks);
     }
+    Ranges r;
+    for (int k = 0; k < nchunks; ++k) r.push_back({leaf.sL[cut[k]], cut[k + 1] < nleaf ? leaf.sL[cut[k + 1]] : T->S});
     return r;
 }
 
@@ -628,6 +670,10 @@ void absorb_usage(const fx_tree* T) {
     FxSizeHint& h = T->hint;
     // sizes per row range of that call, scaled to the whole traversal
     const long nc = std::max(1, T->usage_nchunks);
+    if (T->usage_nchunks == h.range_chunks) {
+        h.range_e_in = std::max({h.range_e_in, u.e_in, u.need_in});
+        h.range_e_leaf = std::max({h.range_e_leaf, u.e_leaf, u.need_leaf, u.need_in});
+    }
     h.e_in = std::max(h.e_in, u.e_in * nc);
     h.e_leaf = std::max(h.e_leaf, u.e_leaf * nc);
     // a level that overflowed asked for need entries (later levels are unknown: at least that)
@@ -763,18 +809,22 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
 
     // ---- capacities ----
     auto caps_from_hint = [&](Sys& s, int nch) {
+        const FxSizeHint& h = s.T->hint;
         long ei, el;
         if (o.max_frontier_entries > 0) {
             ei = el = o.max_frontier_entries;
+        } else if (nch > 1 && h.range_chunks == nch && h.range_e_in > 0) {
+            // measured for these row ranges (a small margin for another density)
+            ei = (long)(1.125 * (double)h.range_e_in) + 1024;
+            el = (long)(1.125 * (double)h.range_e_leaf) + 1024;
         } else {
             // the whole traversal's sizes, shared by nch row ranges (which are not
             // equally large: a larger margin when split)
-            const FxSizeHint& h = s.T->hint;
             const double m = nch > 1 ? 1.5 : 1.25;
             ei = (long)(m * (double)h.e_in / nch) + 1024;
             el = (long)(m * (double)h.e_leaf / nch) + 1024;
         }
-        s.caps = make_caps(s.T, ei, el);
+        s.caps = make_caps(s.T, ei, el, nch > 1 ? row_ranges(s.T, nch) : whole_rows(s.T));
     };
     int nchunks = 1;
     if (noalloc && o.max_frontier_entries == 0) {
@@ -782,11 +832,11 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
         long lo = 1, hi = kEntryMax;
         while (lo < hi) {
             const long mid = lo + (hi - lo + 1) / 2;
-            for (auto& s : sys) s.caps = make_caps(s.T, mid, 4 * mid);
+            for (auto& s : sys) s.caps = make_caps(s.T, mid, 4 * mid, whole_rows(s.T));
             if (layout(nullptr) <= scratch_bytes) lo = mid;
             else hi = mid - 1;
         }
-        for (auto& s : sys) s.caps = make_caps(s.T, lo, 4 * lo);
+        for (auto& s : sys) s.caps = make_caps(s.T, lo, 4 * lo, whole_rows(s.T));
         nchunks = 1;
     } else {
         bool learn = false;
@@ -794,10 +844,11 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
         if (learn) {
             // first call on a tree: traverse only, growing the capacity of the
             // level that overflowed until every level fits; the hint is then
-            // the exact sizes seen
+            // the exact sizes seen (and, for one system, the leaf entries per row)
             std::vector<long> want_in(count, 1L << 16), want_leaf(count, 1L << 18);
             for (int attempt = 0; attempt < 64; ++attempt) {
-                for (int i = 0; i < count; ++i) sys[i].caps = make_caps(sys[i].T, want_in[i], want_leaf[i]);
+                for (int i = 0; i < count; ++i)
+                    sys[i].caps = make_caps(sys[i].T, want_in[i], want_leaf[i], whole_rows(sys[i].T));
                 acquire();
                 fx_launch_fill_u64((unsigned long long*)sh.run, sizeof(FxDevRun) / 8, 0ull, st);
                 for (auto& s : sys) {
@@ -805,6 +856,16 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
                     s.a_lo = 0;
                     s.a_hi = s.T->S;
                     traverse(s, tau, o.tau_ovlp, allow_sym, true, st, sh);
+                }
+                const int nleaf0 = (int)sys[0].T->levels.back().sL.size();
+                std::vector<unsigned long long> rows(nleaf0, 0ull);
+                if (count == 1) {
+                    const int lv = (int)sys[0].T->levels.size() - 1;
+                    fx_launch_fill_u64(sh.rows, nleaf0, 0ull, st);
+                    fx_launch_leaf_rows(sys[0].b.ad[lv & 1], sys[0].b.off[lv & 1], sys[0].cnt, lv,
+                                        sys[0].caps.items, sh.rows, st);
+                    FX_HIP(hipMemcpyAsync(rows.data(), sh.rows, sizeof(unsigned long long) * nleaf0,
+                                          hipMemcpyDeviceToHost, st));
                 }
                 std::vector<FxDevCounts> hc(count);
                 FX_HIP(hipMemcpyAsync(hc.data(), sh.cnts, sizeof(FxDevCounts) * count, hipMemcpyDeviceToHost, st));
@@ -835,6 +896,7 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
                     }
                     h.e_in = ein;
                     h.e_leaf = std::max(1L, hc[i].ne[nl - 1]);
+                    if (count == 1) h.leaf_rows.assign(rows.begin(), rows.end());
                 }
                 if (!again) break;
             }
@@ -843,13 +905,91 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
             nchunks = chunks_for(sys[0].T->hint.e_in, sys[0].T->hint.e_leaf);
         for (auto& s : sys) caps_from_hint(s, nchunks);
         if (count == 1 && o.max_frontier_entries == 0) {
-            // fewer entries per pass when the device cannot hold them: K row ranges one after another
+            // K row ranges one after another when one pass would need more than
+            // the workspace budget (or than the device holds)
+            const fx_tree* T = sys[0].T;
+            FxSizeHint& h = T->hint;
+            const int nleaf = (int)T->levels.back().sL.size();
+            size_t budget = o.max_workspace_bytes > 0 ? (size_t)o.max_workspace_bytes
+                            : o.max_workspace_bytes == 0 ? kDefaultWorkspace : SIZE_MAX;
             const size_t avail = free_device_bytes();
-            while (avail > 0 && layout(nullptr) > avail / 10 * 8 &&
-                   nchunks < (int)sys[0].T->levels.back().sL.size()) {
-                nchunks *= 2;
-                caps_from_hint(sys[0], nchunks);
+            if (avail > 0) budget = std::min(budget, avail / 10 * 8);
+            auto bytes_at = [&](int nch) {
+                caps_from_hint(sys[0], nch);
+                return layout(nullptr);
+            };
+            // the fewest row ranges within `limit`: doubling, then bisection
+            auto fewest = [&](int from, size_t limit) {
+                if (bytes_at(from) <= limit || from >= nleaf) return from;
+                int lo = from, hi = from;
+                while (hi < nleaf) {
+                    hi = (int)std::min<long>(nleaf, 2L * hi);
+                    if (bytes_at(hi) <= limit) break;
+                    lo = hi;
+                }
+                if (bytes_at(hi) > limit) return hi;
+                while (hi - lo > 1) {
+                    const int mid = lo + (hi - lo) / 2;
+                    if (bytes_at(mid) <= limit) hi = mid;
+                    else lo = mid;
+                }
+                return hi;
+            };
+            const bool planned = h.plan_chunks > 0 && h.plan_budget == budget && h.plan_e_in == h.e_in &&
+                                 h.plan_e_leaf == h.e_leaf && h.plan_range_chunks == h.range_chunks;
+            if (planned) {
+                nchunks = h.plan_chunks;
+            } else if (layout(nullptr) > budget) {
+                // a budget below the part that does not shrink with more ranges
+                // (densities' norms, accumulators) is met as closely as is useful
+                const size_t floor_bytes = bytes_at(nleaf);
+                const size_t limit = std::max(budget, floor_bytes + floor_bytes / 4);
+                nchunks = fewest(nchunks, limit);
+                // the entries of each of these ranges, measured once (traversal only)
+                for (int round = 0; round < 3 && nchunks > 1 && h.range_chunks != nchunks; ++round) {
+                    const Ranges rr = row_ranges(T, nchunks);
+                    caps_from_hint(sys[0], nchunks);
+                    long ei = sys[0].caps.e_in, el = sys[0].caps.e_leaf;
+                    bool measured = false;
+                    for (int attempt = 0; attempt < 32 && !measured; ++attempt) {
+                        sys[0].caps = make_caps(T, ei, el, rr);
+                        acquire();
+                        fx_launch_fill_u64((unsigned long long*)sh.run, sizeof(FxDevRun) / 8, 0ull, st);
+                        density_norms(sys[0], ndens, allow_sym, st);
+                        for (const auto& r : rr) {
+                            sys[0].a_lo = r.first;
+                            sys[0].a_hi = r.second;
+                            traverse(sys[0], tau, o.tau_ovlp, allow_sym, r.first == 0, st, sh);
+                        }
+                        FxDevRun run;
+                        FX_HIP(hipMemcpyAsync(&run, sh.run, sizeof(run), hipMemcpyDeviceToHost, st));
+                        FX_HIP(hipStreamSynchronize(st));
+                        release();
+                        if (!run.overflow) {
+                            h.range_chunks = nchunks;
+                            h.range_e_in = std::max(1L, run.e_in);
+                            h.range_e_leaf = std::max(1L, run.e_leaf);
+                            measured = true;
+                        } else if (run.need_in > kEntryMax || run.need_leaf > kEntryMax) {
+                            break;
+                        } else {
+                            ei = std::max(ei, run.need_in + run.need_in / 8);
+                            el = std::max(el, run.need_leaf + run.need_leaf / 8);
+                        }
+                    }
+                    if (!measured) break;
+                    // uneven ranges can need more than the estimate: more of them
+                    if (bytes_at(nchunks) > limit && nchunks < nleaf) nchunks = fewest(nchunks + 1, limit);
+                }
             }
+            if (!planned) {
+                h.plan_chunks = nchunks;
+                h.plan_budget = budget;
+                h.plan_e_in = h.e_in;
+                h.plan_e_leaf = h.e_leaf;
+                h.plan_range_chunks = h.range_chunks;
+            }
+            caps_from_hint(sys[0], nchunks);
         }
     }
 
@@ -1097,6 +1237,7 @@ void fx_exchange_opts_init(fx_exchange_opts* o) {
     o->symmetry = FX_SYM_AUTO;
     o->leaf_screen = FX_LEAF_SHELL;
     o->tau_ovlp = 0.0;
+    o->max_workspace_bytes = 0;
 }
 
 fx_status fx_exchange_ex(const fx_tree* tree, const double* P, double tau, double* K, const fx_exchange_opts* opts,

@@ -157,6 +157,15 @@ struct Plan {
 struct FxSizeHint {
     long e_in = 0;      // largest entry count of an inner level of the whole traversal (0: not known yet)
     long e_leaf = 0;    // leaf-level entry count of the whole traversal
+    // measured for one split of K into row ranges: the largest inner-level and
+    // leaf-level entry counts of any one range (0: not measured)
+    int range_chunks = 0;
+    long range_e_in = 0, range_e_leaf = 0;
+    std::vector<long> leaf_rows;   // leaf entries per leaf row of the whole traversal (empty: unknown)
+    // the row-range count last chosen, and what it was chosen for
+    int plan_chunks = 0, plan_range_chunks = 0;
+    size_t plan_budget = 0;
+    long plan_e_in = 0, plan_e_leaf = 0;
 };
 struct FxGraphCache;                        // fx_exec.cpp
 void fx_graph_cache_free(FxGraphCache* g);  // fx_exec.cpp

@@ -70,6 +70,8 @@ void fx_launch_expand_write(const FxLevelArgs& L, long n_max, const uint8_t* mas
                             const long* adpos, int2* bc_next, int* parent_next, hipStream_t st);
 void fx_launch_unit_count(const int2* items, const FxDevCounts* cnt, int lv, long cap, const int* leaf_lofs,
                           const int* leaf_lsh, int* out, hipStream_t st);
+void fx_launch_leaf_rows(const int2* items, const long* off, const FxDevCounts* cnt, int lv, long cap,
+                         unsigned long long* rows, hipStream_t st);
 void fx_launch_unit_bounds(const long* upos, long cap, FxDevCounts* cnt, hipStream_t st);
 void fx_launch_unit_write(const int2* items, const FxDevCounts* cnt, int lv, long cap, const int* leaf_lofs,
                           const int* leaf_lsh, const long* upos, int* units, hipStream_t st);

@@ -717,6 +717,21 @@ void fx_launch_unit_count(const int2* items, const FxDevCounts* cnt, int lv, lon
                        leaf_lsh, out);
 }
 
+// Leaf entries per leaf row: for every leaf item (A, D), its entry count is
+// added to row A.  Used to cut K into row ranges of similar size.
+__global__ __launch_bounds__(256) void fx_k_leaf_rows(const int2* __restrict__ items, const long* __restrict__ off,
+                                                      const FxDevCounts* cnt, int lv, long cap,
+                                                      unsigned long long* __restrict__ rows) {
+    const long nitems = cnt->nad[lv];
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < cap && p < nitems; p += (long)gridDim.x * blockDim.x)
+        atomicAdd(rows + items[p].x, (unsigned long long)(off[p + 1] - off[p]));
+}
+
+void fx_launch_leaf_rows(const int2* items, const long* off, const FxDevCounts* cnt, int lv, long cap,
+                         unsigned long long* rows, hipStream_t st) {
+    hipLaunchKernelGGL(fx_k_leaf_rows, dim3(fx_grid_for(cap, 256)), dim3(256), 0, st, items, off, cnt, lv, cap, rows);
+}
+
 // unit list bounds per (la, ld) from the scanned counts
 __global__ void fx_k_unit_bounds(const long* __restrict__ upos, long cap, FxDevCounts* cnt) {
     const int k = threadIdx.x;

@@ -43,7 +43,7 @@ class fx_exchange_opts(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("max_frontier_entries", ctypes.c_int64), ("profile", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("symmetry", ctypes.c_int32), ("leaf_screen", ctypes.c_int32),
-                ("tau_ovlp", ctypes.c_double)]
+                ("tau_ovlp", ctypes.c_double), ("max_workspace_bytes", ctypes.c_int64)]
 
 
 class fx_train_opts(ctypes.Structure):
@@ -293,11 +293,12 @@ def opts_init():
 
 def make_opts(precision=FX_PREC_FP64, fp32_threshold=1e-5, schedule=FX_SCHED_BOUND, costmodel=None, alpha=1.0,
               beta=0.0, max_frontier_entries=0, profile=False, use_graph=False, symmetry=FX_SYM_AUTO,
-              leaf_screen=FX_LEAF_SHELL, tau_ovlp=0.0):
+              leaf_screen=FX_LEAF_SHELL, tau_ovlp=0.0, max_workspace_bytes=0):
     return fx_exchange_opts(int(precision), float(fp32_threshold), int(schedule),
                             ctypes.c_void_p(costmodel.handle if costmodel is not None else None),
                             float(alpha), float(beta), int(max_frontier_entries), int(bool(profile)),
-                            int(bool(use_graph)), int(symmetry), int(leaf_screen), float(tau_ovlp))
+                            int(bool(use_graph)), int(symmetry), int(leaf_screen), float(tau_ovlp),
+                            int(max_workspace_bytes))
 
 
 def fx_exchange(tree: Tree, P, tau, K, stream=None):

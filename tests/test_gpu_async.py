@@ -90,6 +90,27 @@ def test_overflow_without_waiting_gives_nan_and_waiting_splits(mid):
     assert st["quartets"] == st0["quartets"]
 
 
+def test_workspace_budget_runs_row_ranges(mid):
+    """A workspace budget below what one pass needs: the traversal runs over
+    K row ranges (cut where the leaf entries of the first call balance, each
+    range's sizes measured once), the workspace stays within the budget, and
+    K is bitwise the same, eager and replayed."""
+    s, tree, P, Kref, st0 = mid
+    budget = st0["workspace_bytes"] // 4
+    say(f"gpu: workspace budget {budget} of {st0['workspace_bytes']} bytes")
+    opts = fx.make_opts(precision=fx.FX_PREC_MIXED, max_workspace_bytes=budget)
+    K, st = fx.fx_exchange_ex(tree, P, s.tau, torch.zeros_like(P), opts)
+    assert st["chunks"] > st0["chunks"] and st["overflow"] == 0
+    assert st["workspace_bytes"] <= budget
+    assert torch.equal(K, Kref) and st["quartets"] == st0["quartets"]
+    g = fx.make_opts(precision=fx.FX_PREC_MIXED, max_workspace_bytes=budget, use_graph=True)
+    for i in range(2):
+        K.fill_(float(i + 1))
+        fx.fx_exchange_ex(tree, P, s.tau, K, g, stats=False)
+        torch.cuda.synchronize()
+        assert torch.equal(K, Kref), f"replay {i}"
+
+
 def test_first_call_learns_capacities():
     """A fresh tree: the first call sizes its buffers by a traversal-only
     pass; later calls need no more than 25% above the sizes seen."""

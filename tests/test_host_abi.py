@@ -169,6 +169,7 @@ def test_exchange_opts_init_fills_documented_defaults():
     assert o.alpha == 1.0 and o.beta == 0.0
     assert o.max_frontier_entries == 0 and o.profile == 0 and o.use_graph == 0
     assert o.symmetry == fx.FX_SYM_AUTO and o.leaf_screen == fx.FX_LEAF_SHELL
+    assert o.tau_ovlp == 0.0 and o.max_workspace_bytes == 0
     d = fx.make_opts()
     for name, _ in fx.fx_exchange_opts._fields_:
         if name != "costmodel":
