@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBPS = 8000.0
 LNAME = "spd"
 
 
@@ -50,6 +51,20 @@ def kernel_sources_hash(kernel):
             return None
         h.update(open(path, "rb").read())
     return h.hexdigest()[:16]
+
+
+def tuning_table_info():
+    """Hash and size of the tuning table the library was generated and launched with."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_1401_6961_amd", "tuning_gfx950.json")
+    if not os.path.exists(path):
+        return None
+    raw = open(path, "rb").read()
+    t = json.loads(raw)
+    gen = t.get("generator", {})
+    return {"path": os.path.relpath(path, ROOT), "sha256": hashlib.sha256(raw).hexdigest()[:16],
+            "launch_entries": len(t.get("classes", {})), "generator_kernels": len(gen.get("kernels", {})),
+            "generator_tuned": gen.get("tuned")}
 
 
 def profiled_traffic(kernel):
@@ -264,6 +279,12 @@ def main():
         top.append({"class": cname(cc), "prec": tg, "s": float(cs[cc, pp]), "tflops": float(fl / cs[cc, pp] / 1e12),
                     "quartets": qq})
     roofline["top_class_kernels"] = top
+    if traffic:
+        # the roof the counters put the kernel against: its HBM bytes (private-memory
+        # traffic included) per second against 8 TB/s, next to its algorithmic ALU fraction
+        hbm_frac = traffic / avg_launch_s / (HBM_PEAK_GBPS * 1e9)
+        roofline["traffic_frac_of_hbm_peak"] = hbm_frac
+        roofline["measured_bound"] = "hbm" if hbm_frac > roofline["frac"] else "alu"
 
     extra = {}
     if not args.no_fp64:
@@ -318,7 +339,8 @@ def main():
            "alg_tflops": st["flops"] / (elapsed / args.steps) / 1e12, "tree_build_s": t_tree,
            "workspace_bytes": st["workspace_bytes"], "graph": st["graph_nodes"] == 1,
            "schedule": "mlp" if model is not None else "bound", "profiled_K_equal": same_profiled,
-           "autotuned_entries": tuned, "roofline": roofline, "cpu_baseline": cpu}
+           "autotuned_entries": tuned, "tuning_table": tuning_table_info(), "roofline": roofline,
+           "cpu_baseline": cpu}
     out.update(extra)
     print(json.dumps(out))
 

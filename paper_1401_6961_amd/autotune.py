@@ -12,6 +12,18 @@ not depend on these choices (tests check this bitwise).
     python -m paper_1401_6961_amd.autotune --natom 300 --out tuning_gfx950.json
 
 apply(path) loads a table into the library (process-wide).
+
+The generator's per-kernel choices (the "generator" section: routine form,
+pairing, waves per SIMD, one-pass mixed precision) are compile-time, so
+they are tuned on candidate libraries, each built from the current table
+with one choice changed for every kernel it applies to; a class's kernels
+are timed in every candidate and the candidate fastest for that class
+gives the class's entries (classes are separate kernels, so their choices
+do not interact):
+
+    python -m paper_1401_6961_amd.autotune --generator build --dir DIR    # CPU
+    python -m paper_1401_6961_amd.autotune --generator measure --dir DIR  # GPU
+    python -m paper_1401_6961_amd.autotune --generator choose --dir DIR   # CPU, rewrites the table
 """
 from __future__ import annotations
 
@@ -89,13 +101,164 @@ def tune(natom=300, with_d=True, seed=1002, repeats=2, log=print):
     return table
 
 
+# ---------------------------------------------------------------------------
+# generator choices
+# ---------------------------------------------------------------------------
+CANDIDATES = ("current", "folded", "folded_w2", "unpaired", "waves2", "dual_all", "dual_none")
+
+
+def candidate_kernels(name, kernels):
+    """The generator entries of candidate `name`, derived from `kernels`."""
+    k = {key: dict(e) for key, e in kernels.items()}
+    routines = [key for key in k if not key.endswith(":mix")]
+    classes = sorted({key.split(":")[0] for key in routines})
+    if name == "register":
+        for key in routines:
+            k[key] = {"form": "register", "waves": 1}
+    elif name.startswith("folded"):
+        w = int(name[-1]) if name[-2:-1] == "w" else 1
+        for key in routines:
+            if "d" in key.split(":")[0]:
+                k[key] = {"form": "folded", "paired": True, "waves": w}
+    elif name == "unpaired":
+        for key in routines:
+            if k[key].get("form", "register") != "register":
+                k[key]["paired"] = False
+    elif name == "waves2":
+        for key in k:
+            k[key]["waves"] = 2
+    elif name == "dual_all":
+        for c in classes:
+            k.setdefault(f"{c}:mix", {"waves": 1})
+    elif name == "dual_none":
+        k = {key: e for key, e in k.items() if not key.endswith(":mix")}
+    elif name != "current":
+        raise ValueError(f"unknown candidate {name}")
+    return k
+
+
+def generator_build(d, table_path=DEFAULT_TABLE, names=CANDIDATES, log=print):
+    """Candidate libraries under d/<name>/ (objects shared with the package build)."""
+    from . import build as B
+    table = json.load(open(table_path))
+    for name in names:
+        cdir = os.path.join(d, name)
+        os.makedirs(os.path.join(cdir, "gen"), exist_ok=True)
+        t = dict(table)
+        t["generator"] = dict(table["generator"], kernels=candidate_kernels(name, table["generator"]["kernels"]))
+        tp = os.path.join(cdir, "table.json")
+        with open(tp, "w") as fh:
+            json.dump(t, fh, indent=1, sort_keys=True)
+        log(f"autotune: building candidate {name}")
+        B.build(incremental=True, table=tp, gen=os.path.join(cdir, "gen"), lib=os.path.join(cdir, "libfx.so"))
+
+
+def time_classes(natom, repeats, seed=1002):
+    """Per (class, precision slot) kernel seconds of the mixed build of the
+    natom s+p+d cluster with the loaded library (least of `repeats`)."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    from . import fx
+    apply()
+    system = synthetic.cluster(natom)
+    tree = fx.build_quadtree_from(system)
+    P = torch.from_numpy(system.P).cuda()
+    K = torch.zeros_like(P)
+    fx.fx_exchange_ex(tree, P, system.tau, K, fx.make_opts(precision=fx.FX_PREC_MIXED), stats=False)
+    best = None
+    for _ in range(repeats):
+        _, st = fx.fx_exchange_ex(tree, P, system.tau, K, fx.make_opts(precision=fx.FX_PREC_MIXED, profile=True))
+        cs = st["class_seconds"]
+        best = cs if best is None else np.minimum(best, cs)
+    return best
+
+
+def generator_measure(d, natom=1000, repeats=2, names=CANDIDATES, log=print):
+    """Time every candidate library in a child process of its own (a library
+    is loaded once per process); d/<name>/times.json."""
+    import subprocess
+    for name in names:
+        lib = os.path.join(d, name, "libfx.so")
+        if not os.path.exists(lib):
+            continue
+        out = os.path.join(d, name, "times.json")
+        log(f"autotune: timing candidate {name}")
+        r = subprocess.run([sys.executable, "-m", "paper_1401_6961_amd.autotune", "--time-lib", lib, "--natom",
+                            str(natom), "--repeats", str(repeats), "--out", out],
+                           cwd=os.path.dirname(HERE), timeout=900)
+        if r.returncode != 0:
+            raise RuntimeError(f"timing candidate {name} failed with status {r.returncode}")
+
+
+def generator_choose(d, table_path=DEFAULT_TABLE, names=CANDIDATES, log=print):
+    """Per class, the entries of the candidate whose kernels of that class
+    took least time in the mixed build (both precision slots summed)."""
+    import numpy as np
+    table = json.load(open(table_path))
+    cur = table["generator"]["kernels"]
+    times, kern = {}, {}
+    for name in names:
+        tp = os.path.join(d, name, "times.json")
+        if os.path.exists(tp):
+            times[name] = np.asarray(json.load(open(tp))["class_seconds"])
+            kern[name] = json.load(open(os.path.join(d, name, "table.json")))["generator"]["kernels"]
+    if "current" not in times:
+        raise RuntimeError("the current table's candidate was not timed")
+    L = "spd"
+    new, chosen = {}, {}
+    for c in range(81):
+        cls = L[c // 27] + L[(c // 9) % 3] + L[(c // 3) % 3] + L[c % 3]
+        best = min(times, key=lambda nm: (float(times[nm][c].sum()) if times[nm][c].sum() > 0 else 1e30,
+                                          nm != "current"))
+        chosen[cls] = (best, float(times[best][c].sum()), float(times["current"][c].sum()))
+        for key, e in kern[best].items():
+            if key.split(":")[0] == cls:
+                new[key] = e
+    before = sum(v[2] for v in chosen.values())
+    after = sum(v[1] for v in chosen.values())
+    changed = {c: v[0] for c, v in chosen.items() if v[0] != "current"}
+    log(f"autotune: class time {before:.3f} s with the current table, {after:.3f} s with the choices; "
+        f"{len(changed)} classes changed: {changed}")
+    table["generator"] = dict(table["generator"], kernels=new,
+                              tuned={"candidates": sorted(times), "class_seconds_before": before,
+                                     "class_seconds_after": after})
+    with open(table_path, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--natom", type=int, default=300)
     ap.add_argument("--sp", action="store_true", help="s+p shells only")
     ap.add_argument("--out", default=DEFAULT_TABLE)
+    ap.add_argument("--generator", choices=["build", "measure", "choose"], help="tune the generator's choices")
+    ap.add_argument("--dir", default=os.path.join(os.path.dirname(HERE), "_autotune"))
+    ap.add_argument("--candidates", default=",".join(CANDIDATES))
+    ap.add_argument("--time-lib", help=argparse.SUPPRESS)
+    ap.add_argument("--repeats", type=int, default=2)
     args = ap.parse_args()
+    log = lambda m: print(m, flush=True)  # noqa: E731
+    names = tuple(args.candidates.split(","))
+    if args.time_lib:
+        from . import fx
+        fx.LIB_PATH = args.time_lib
+        cs = time_classes(args.natom, args.repeats)
+        with open(args.out, "w") as fh:
+            json.dump({"lib": args.time_lib, "natom": args.natom, "class_seconds": cs.tolist()}, fh)
+        log(f"autotune: {args.time_lib}: class time {cs.sum():.3f} s")
+        return
+    if args.generator == "build":
+        return generator_build(args.dir, names=names, log=log)
+    if args.generator == "measure":
+        return generator_measure(args.dir, args.natom, args.repeats, names=names, log=log)
+    if args.generator == "choose":
+        return generator_choose(args.dir, names=names, log=log)
     table = tune(args.natom, with_d=not args.sp, log=lambda m: print(m, flush=True))
+    if os.path.exists(args.out):
+        # keep the generator's choices
+        table = dict(json.load(open(args.out)), **table)
     with open(args.out, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
     print(f"autotune: wrote {len(table['classes'])} entries to {args.out}", flush=True)

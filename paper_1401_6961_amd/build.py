@@ -22,16 +22,21 @@ LIB = os.path.join(PKG, "libfx.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
-             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-I", CSRC, "-I", GEN, "-I", os.path.join(ROOT, "include"),
-             "-Wno-unused-variable", "-Wno-unused-lambda-capture"]
+
+def _flags(gen=GEN):
+    return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-I", CSRC, "-I", gen, "-I", os.path.join(ROOT, "include"),
+            "-Wno-unused-variable", "-Wno-unused-lambda-capture"]
 
 
-def _sources():
+HIP_FLAGS = _flags()
+
+
+def _sources(gen=GEN):
     srcs = [os.path.join(CSRC, f) for f in ("fx_kernels.hip", "fx_host.cpp", "fx_exec.cpp", "fx_noalloc.cpp", "fx_costmodel.hip")
             if os.path.exists(os.path.join(CSRC, f))]
-    srcs += sorted(os.path.join(GEN, f) for f in os.listdir(GEN) if f.endswith(".hip"))
+    srcs += sorted(os.path.join(gen, f) for f in os.listdir(gen) if f.endswith(".hip"))
     return srcs
 
 
@@ -40,9 +45,9 @@ def _sources():
 CLASS_HEADERS = ("fx_eri_common.h", "fx_internal.h")
 
 
-def _headers_digest(only=None):
+def _headers_digest(only=None, gen=GEN):
     h = hashlib.sha256()
-    for d in (CSRC, GEN, os.path.join(ROOT, "include")):
+    for d in (CSRC, gen, os.path.join(ROOT, "include")):
         for f in sorted(os.listdir(d)):
             if f.endswith(".h") and (only is None or f in only):
                 h.update(f.encode())
@@ -55,16 +60,17 @@ def _digest_for(src, full, classes):
     return classes if os.path.basename(src).startswith("eri_") else full
 
 
-def _compile(src, hdr_digest, incremental):
+def _compile(src, hdr_digest, incremental, flags=HIP_FLAGS):
     h = hashlib.sha256()
     h.update(open(src, "rb").read())
     h.update(hdr_digest.encode())
+    # the flags without the generation directory: its headers are in hdr_digest
     h.update(" ".join(HIP_FLAGS).encode())
     obj = os.path.join(BUILD, os.path.basename(src) + "." + h.hexdigest()[:16] + ".o")
     if incremental and os.path.exists(obj):
         return obj
     tmp = obj + ".tmp"
-    cmd = [HIPCC] + HIP_FLAGS + ["-x", "hip", "-c", src, "-o", tmp]
+    cmd = [HIPCC] + flags + ["-x", "hip", "-c", src, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {src}\n{r.stderr[-4000:]}")
@@ -72,27 +78,37 @@ def _compile(src, hdr_digest, incremental):
     return obj
 
 
-def build(incremental: bool | None = None, jobs: int | None = None) -> str:
+def build(incremental: bool | None = None, jobs: int | None = None, table: str | None = None,
+          gen: str = GEN, lib: str = LIB) -> str:
+    """Generate the class kernels from the tuning table's generator choices
+    (`table`, default the package's), compile and link `lib`.  Another
+    table is built into its own `gen` directory and `lib` (the autotuner's
+    candidate libraries)."""
     if incremental is None:
         incremental = os.environ.get("FX_BUILD_INCREMENTAL", "0") == "1"
     os.makedirs(BUILD, exist_ok=True)
     sys.path.insert(0, CSRC)
     import gen_eri  # noqa: E402
-    gen_eri.main(GEN)
-    full, classes = _headers_digest(), _headers_digest(CLASS_HEADERS)
-    srcs = _sources()
+    gen_eri.load_choices(table or gen_eri.TABLE)
+    try:
+        gen_eri.main(gen)
+    finally:
+        gen_eri.load_choices()
+    full, classes = _headers_digest(gen=gen), _headers_digest(CLASS_HEADERS, gen=gen)
+    flags = _flags(gen)
+    srcs = _sources(gen)
     # biggest sources first so the long compiles start early
     srcs.sort(key=lambda s: -os.path.getsize(s))
     jobs = jobs or min(16, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, _digest_for(s, full, classes), incremental), srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, _digest_for(s, full, classes), incremental, flags), srcs))
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed\n{r.stderr[-4000:]}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -828,65 +828,54 @@ def pair_size(l1, l2):
 COOP_MIN, THREAD_MAX = 100, 1 << 30
 
 
-# Waves per SIMD that the register allocation of a one-quartet-per-lane
-# kernel must allow (default 1, i.e. up to 512 registers per lane; set below
-# for some staged kernels).  Of the register-form kernels only (dd|dd) FP64
-# ran faster at two waves (-21%), and its staged form beats that.
-MIN_WAVES = {}
+# Per-kernel generator choices, read from the "generator" section of the
+# tuning table (tuning_gfx950.json, written by the autotuner from per-kernel
+# timings): for each (class, precision) the form of the one-quartet-per-lane
+# routine -- "register" (gen_class), "staged" or "folded" (gen_class_staged
+# without / with the folded ket HRR), "chunked" (gen_class_chunked, with
+# "chunks" and "xreg") --, whether staged forms evaluate two primitive
+# quartets per pass ("paired"), and the waves per SIMD that the register
+# allocation must allow ("waves"); a "<class>:mix" entry builds the class's
+# mixed-precision kernel that screens each candidate once and runs both
+# precisions in one pass, with its own "waves".  Without a table every
+# kernel is the register form at one wave, in two passes.
+TABLE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tuning_gfx950.json")
 
-# (class, precision) pairs whose one-quartet-per-lane routine is the staged
-# form (gen_class_staged).
-# Chosen per kernel by measurement on the 1000-atom s+p+d cluster (both forms
-# built for 19 classes, the faster kept): the staged form wins wherever the
-# register form spills kilobytes per lane -- every FP64 class with two or more
-# d shells, and FP32 with three or four -- and loses where it spills little
-# or nothing (FP32 with two d shells, all (pp|pd)-type classes).
-STAGED = {(c, "f64") for c in ("sddd", "ppdd", "pdpd", "pddp", "pddd", "dsdd", "dppd", "dpdp", "dpdd", "ddsd", "ddpp",
-                               "ddpd", "ddds", "dddp", "dddd")} | \
-         {(c, "f32") for c in ("pddd", "dpdd", "ddpd", "dddp", "dddd")}
-# Staged classes evaluated one primitive quartet per pass: (dd|dd) has a
-# single primitive quartet in the usual bases, and for the classes with an s
-# shell (three primitives) the zero-weight padding of an odd count cost more
-# than pairing saved (measured +10-25%); pairing saved 4-20% elsewhere.
-UNPAIRED = {"dddd", "ddds", "ddsd", "dsdd", "sddd"}
-
-# Staged kernels with the folded ket HRR (gen_class_staged(fold=True)):
-# 17-55% faster than forming the bra-transferred block in private memory,
-# except (dd|dd) FP32 (4% slower).
-FOLD = set(STAGED) - {("dddd", "f32")}
-# Classes whose mixed-precision build screens each candidate once and runs
-# both precisions in one kernel (FX_DUAL_KERNEL) by default: chosen per class
-# on the 1000-atom cluster (both forms measured, one pass kept where at least
-# 2% faster).  It saves the second screening pass; it loses where the FP64
-# and FP32 routines want different register budgets ((dd|dd), the FP32
-# classes with two d shells in the register form).
-DUAL = {"dddp", "ddds", "ddpp", "ddps", "ddsd", "ddsp", "dpdd", "dpds", "dppd", "dpsd", "dpss", "dsdp", "dsds", "dspd",
-        "dsps", "dssd", "dssp", "dsss", "pddd", "pdds", "pdsd", "pdss", "ppdd", "pppp", "ppps", "ppsp", "psdd", "psds",
-        "pspp", "psps", "pssd", "pssp", "psss", "sddd", "sddp", "sdpd", "sdps", "sdsd", "sdsp", "sdss", "spdd", "spds",
-        "sppp", "spps", "spsd", "spsp", "spss", "ssdp", "ssds", "sspd", "sspp", "ssps", "sssd", "sssp", "ssss"}
-
-# With the fold, three FP32 classes with two d shells gain too (4-12%); the
-# other FP32 classes with one or two d shells and the (pp|pd)-type classes
-# stay faster in the register form.
-STAGED |= {("ddpp", "f32"), ("dppd", "f32"), ("ppdd", "f32")}
-FOLD |= {("ddpp", "f32"), ("dppd", "f32"), ("ppdd", "f32")}
-
-# Staged kernels measured at one, two and three waves per SIMD (1000-atom
-# cluster); the fastest kept.  With the folded ket HRR most run best at one
-# wave (they need ~250 registers); (dd|dd) FP64 and the FP64 classes with an s
-# shell run best at three and two.  Forcing three or four waves on
-# register-form kernels that fit at one or two made them spill and run
-# about three times slower.
-MIN_WAVES = {("dddd", "f64"): 3} | {(c, "f64"): 2 for c in ("ddds", "ddsd", "dsdd", "sddd")}
-# one-pass kernels: one wave except five small classes measured faster at two
-MIN_WAVES.update({(c, "mix"): 2 for c in ("sdsd", "dsds", "dssd", "dsss", "spss")})
+STAGED, FOLD, UNPAIRED, DUAL = set(), set(), set(), set()
+MIN_WAVES, CHUNKS = {}, {}
+XREG = set()
 
 
-# Staged classes whose primitive loop runs once per chunk of ket columns
-# (gen_class_chunked), by number of chunks: only that chunk's [e0|f0]
-# columns are live, at the price of recomputing the VRR of their shared
-# ancestors in every chunk.
-CHUNKS = {}
+def load_choices(path=TABLE):
+    """Fill the choice sets from a tuning table (empty sets without one)."""
+    global STAGED, FOLD, UNPAIRED, DUAL, MIN_WAVES, CHUNKS, XREG
+    STAGED, FOLD, UNPAIRED, DUAL = set(), set(), set(), set()
+    MIN_WAVES, CHUNKS, XREG = {}, {}, set()
+    if not os.path.exists(path):
+        return
+    import json
+    kernels = json.load(open(path)).get("generator", {}).get("kernels", {})
+    for key, e in kernels.items():
+        cls, prec = key.split(":")
+        if e.get("waves", 1) > 1:
+            MIN_WAVES[(cls, prec)] = int(e["waves"])
+        if prec == "mix":
+            DUAL.add(cls)
+            continue
+        form = e.get("form", "register")
+        if form in ("staged", "folded"):
+            STAGED.add((cls, prec))
+            if form == "folded":
+                FOLD.add((cls, prec))
+        elif form == "chunked":
+            CHUNKS[(cls, prec)] = int(e["chunks"])
+            if e.get("xreg"):
+                XREG.add((cls, prec))
+        if form != "register" and not e.get("paired", True):
+            UNPAIRED.add((cls, prec))
+
+
+load_choices()
 
 
 def variants(la, lb, lc, ld):
@@ -906,9 +895,10 @@ def main(outdir):
             code, fp, fc = gen_class(la, lb, lc, ld, real)
             prec = "f32" if real == "float" else "f64"
             if (cls, prec) in CHUNKS:
-                code = gen_class_chunked(la, lb, lc, ld, real, CHUNKS[(cls, prec)], paired=cls not in UNPAIRED)[0]
+                code = gen_class_chunked(la, lb, lc, ld, real, CHUNKS[(cls, prec)], paired=(cls, prec) not in UNPAIRED,
+                                         xreg=(cls, prec) in XREG)[0]
             elif (cls, prec) in STAGED:
-                code = gen_class_staged(la, lb, lc, ld, real, paired=cls not in UNPAIRED,
+                code = gen_class_staged(la, lb, lc, ld, real, paired=(cls, prec) not in UNPAIRED,
                                         fold=(cls, prec) in FOLD)[0]
             if th:
                 parts.append(code)
