@@ -153,7 +153,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--fp64-steps", type=int, default=5, help="timed FP64 runs (median reported)")
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying the captured call")
-    ap.add_argument("--no-mlp", action="store_true", help="bound-only unit order even if a trained model is shipped")
+    ap.add_argument("--no-mlp", action="store_true", help="do not time the learned unit order beside the headline")
+    ap.add_argument("--learned", action="store_true", help="headline build with the learned unit order")
     ap.add_argument("--workload", default="cluster",
                     choices=["cluster", "batched", "slab-mlp", "copy-probe", "scaling", "multi", "regimes", "chain"],
                     help="cluster: the headline 1000-atom s+p+d build; batched: 64 clusters in one batched "
@@ -164,6 +165,7 @@ def main():
                          "regimes: s+p+d clusters of 125..1000 atoms at the paper's two threshold pairs "
                          "(tau, tau_ovlp) = (1e-8, 1e-11) and (1e-10, 1e-13); chain: 50..3200-atom s+p chains")
     ap.add_argument("--no-tuning", action="store_true", help="ignore the autotuned kernel table")
+    ap.add_argument("--sizes", default="125,250,500,1000,2000", help="atom counts of --workload scaling")
     ap.add_argument("--no-symmetry", action="store_true", help="build every K block (no use of K = K^T)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -206,19 +208,22 @@ def main():
     P = torch.from_numpy(system.P).to(dev)
     K = torch.zeros_like(P)
     sym = fx.FX_SYM_OFF if args.no_symmetry else fx.FX_SYM_AUTO
-    model = None if args.no_mlp else shipped_costmodel(fx)
-    sched = fx.FX_SCHED_MLP if model is not None else fx.FX_SCHED_BOUND
+    model = shipped_costmodel(fx)
+    learned = args.learned and model is not None
+    sched = fx.FX_SCHED_MLP if learned else fx.FX_SCHED_BOUND
     # the build timed: mixed precision, the whole call captured once in a
-    # hipGraph and replayed, units ordered by the learned cost model
+    # hipGraph and replayed, units in bound-only order (the learned order is
+    # timed beside it below and has measured slower: the headline takes the
+    # faster schedule; --learned times the learned one instead)
     opts_head = fx.make_opts(precision=fx.FX_PREC_MIXED, use_graph=not args.no_graph, schedule=sched,
-                             costmodel=model, symmetry=sym)
+                             costmodel=model if learned else None, symmetry=sym)
 
     for i in range(args.warmup):
         log(f"bench: warmup {i}")
         fx.fx_exchange_ex(tree, P, tau, K, opts_head, stats=False)
         torch.cuda.synchronize()
     log(f"bench: timing {args.steps} steps (mixed, graph={not args.no_graph}, "
-        f"schedule={'mlp' if model is not None else 'bound'})")
+        f"schedule={'mlp' if learned else 'bound'})")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -226,6 +231,27 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
+    # the other unit order beside it: alternating runs of both, same K bitwise
+    order_cmp = None
+    if model is not None and not args.no_mlp:
+        other = fx.make_opts(precision=fx.FX_PREC_MIXED, use_graph=not args.no_graph,
+                             schedule=fx.FX_SCHED_BOUND if learned else fx.FX_SCHED_MLP,
+                             costmodel=None if learned else model, symmetry=sym)
+        Ko = torch.zeros_like(P)
+        fx.fx_exchange_ex(tree, P, tau, Ko, other, stats=False)
+        torch.cuda.synchronize()
+        ts = {"head": [], "other": []}
+        for r in range(2):
+            for k, o in ((("head", opts_head), ("other", other)) if r == 0 else (("other", other), ("head", opts_head))):
+                t = time.perf_counter()
+                fx.fx_exchange_ex(tree, P, tau, Ko if k == "other" else K, o, stats=False)
+                torch.cuda.synchronize()
+                ts[k].append(time.perf_counter() - t)
+        log(f"bench: unit orders, headline {ts['head']} s, other {ts['other']} s")
+        lo, bo = (ts["head"], ts["other"]) if learned else (ts["other"], ts["head"])
+        order_cmp = {"learned_order_s": float(np.median(lo)), "bound_order_s": float(np.median(bo)),
+                     "learned_runs_s": lo, "bound_runs_s": bo, "K_bitwise_equal": bool(torch.equal(Ko, K))}
+        del Ko
     # counts of the same build (one more call that waits for its statistics)
     _, st = fx.fx_exchange_ex(tree, P, tau, K, opts_head)
     quartets_eval = st["quartets"]
@@ -241,7 +267,8 @@ def main():
     log("bench: profiled call (per-class HIP events)")
     Kp = torch.zeros_like(P)
     _, stp = fx.fx_exchange_ex(tree, P, tau, Kp, fx.make_opts(precision=fx.FX_PREC_MIXED, profile=True,
-                                                                schedule=sched, costmodel=model, symmetry=sym))
+                                                                schedule=sched, costmodel=model if learned else None,
+                                                                symmetry=sym))
     same_profiled = bool(torch.equal(Kp, K))
     del Kp
     cs, cl, cf, cq = stp["class_seconds"], stp["class_launches"], stp["class_flops"], stp["class_prec_quartets"]
@@ -326,7 +353,7 @@ def main():
            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64+f32", "data": "synthetic",
            "config": {"workload": f"{args.natom}-atom s+p+d cluster, n={system.nbf}, tau=1e-8, mixed precision, "
-                                  f"graph-captured, {'learned' if model is not None else 'bound-only'} unit order",
+                                  f"graph-captured, {'learned' if learned else 'bound-only'} unit order",
                       "natom": args.natom, "nbf": system.nbf, "tau": tau, "parallelism": "single-gpu"},
            "value_note": "value counts the shell quartets whose integrals were evaluated (ERIs); with a "
                          "symmetric density each stands for itself and its mirror, and the K-coverage rate "
@@ -338,7 +365,8 @@ def main():
            "prim_quartets": st["prim_quartets"], "alg_flops": st["flops"],
            "alg_tflops": st["flops"] / (elapsed / args.steps) / 1e12, "tree_build_s": t_tree,
            "workspace_bytes": st["workspace_bytes"], "graph": st["graph_nodes"] == 1,
-           "schedule": "mlp" if model is not None else "bound", "profiled_K_equal": same_profiled,
+           "schedule": "mlp" if learned else "bound", "unit_orders": order_cmp,
+           "profiled_K_equal": same_profiled,
            "autotuned_entries": tuned, "tuning_table": tuning_table_info(), "roofline": roofline,
            "cpu_baseline": cpu}
     out.update(extra)
@@ -368,9 +396,12 @@ def bench_scaling(args, log):
     import torch
     import synthetic
     import paper_1401_6961_amd as fx
-    sizes = (125, 250, 500, 1000, 2000)
+    sizes = tuple(int(x) for x in args.sizes.split(","))
+    # one stderr line per finished K row range: large sizes run many ranges
+    fx.set_progress_stderr("bench: scaling")
     rows = []
     for natom in sizes:
+        log(f"bench: scaling {natom} atoms: first call (sizes its buffers)")
         s = synthetic.cluster(natom, seed=2000 + natom)
         tree = fx.build_quadtree_from(s)
         P = torch.from_numpy(s.P).cuda()
@@ -378,12 +409,14 @@ def bench_scaling(args, log):
         opts = fx.make_opts(precision=fx.FX_PREC_MIXED)
         fx.fx_exchange_ex(tree, P, s.tau, K, opts)
         torch.cuda.synchronize()
+        log(f"bench: scaling {natom} atoms: timed call")
         t = time.perf_counter()
         _, st = fx.fx_exchange_ex(tree, P, s.tau, K, opts)
         torch.cuda.synchronize()
         el = time.perf_counter() - t
         rows.append({"natom": natom, "nbf": s.nbf, "kbuild_s": el, "quartets": st["quartets_covered"],
-                     "quartets_evaluated": st["quartets"]})
+                     "quartets_evaluated": st["quartets"], "workspace_bytes": st["workspace_bytes"],
+                     "row_ranges": st["chunks"] + 1})
         log(f"bench: scaling {natom} atoms n={s.nbf}: {el:.3f} s, {st['quartets_covered']:.3e} quartets")
         del tree, P, K
         torch.cuda.empty_cache()
@@ -391,11 +424,11 @@ def bench_scaling(args, log):
         b["slope_time"] = float(np.log(b["kbuild_s"] / a["kbuild_s"]) / np.log(b["natom"] / a["natom"]))
         b["slope_quartets"] = float(np.log(b["quartets"] / a["quartets"]) / np.log(b["natom"] / a["natom"]))
     last = rows[-1]
-    print(json.dumps({"metric": "K-build s vs size, s+p+d clusters 125..2000 atoms, tau=1e-8, mixed",
+    print(json.dumps({"metric": f"K-build s vs size, s+p+d clusters {args.sizes} atoms, tau=1e-8, mixed",
                       "value": last["quartets"] / last["kbuild_s"], "unit": "quartets/s", "n_gpus": 1, "steps": 1,
                       "warmup": 1, "ms_per_step": 1e3 * last["kbuild_s"], "higher_is_better": True, "scaling": "weak",
                       "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
-                      "config": {"workload": "s+p+d clusters of 125, 250, 500, 1000, 2000 atoms at 0.1 atoms/A^3"},
+                      "config": {"workload": f"s+p+d clusters of {args.sizes} atoms at 0.1 atoms/A^3"},
                       "series": rows}))
 
 

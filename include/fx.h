@@ -351,6 +351,18 @@ typedef void* (*fx_alloc_fn)(size_t bytes, void* stream, void* ctx);
 typedef void (*fx_free_fn)(void* ptr, void* stream, void* ctx);
 fx_status fx_set_allocator(fx_alloc_fn alloc, fx_free_fn free_, void* ctx);
 
+/* Progress of long one-system calls: fn(done, total, ctx) is called on a
+ * runtime thread each time the device finishes one K row range of an eager
+ * call (`total` counts the ranges planned so far; a replayed graph reports
+ * nothing).  The stream waits while fn runs, so fn must return quickly and
+ * must not wait for the stream.  NULL removes it.  Process-wide; not
+ * thread-safe against running calls.  fx_progress_stderr is a ready-made fn
+ * that prints one line per range to stderr (ctx: a NUL-terminated prefix, or
+ * NULL for "fx"). */
+typedef void (*fx_progress_fn)(int32_t done, int32_t total, void* ctx);
+fx_status fx_set_progress(fx_progress_fn fn, void* ctx);
+void fx_progress_stderr(int32_t done, int32_t total, void* ctx);
+
 const char* fx_status_string(fx_status s);
 const char* fx_last_error_message(void);
 

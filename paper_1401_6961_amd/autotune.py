@@ -1,13 +1,15 @@
 """Autotuner of the class kernels.
 
-For every angular-momentum class and precision it chooses the kernel form
-(one quartet per lane, or one quartet per wave with LDS intermediates, where
-both are built) and the launch mapping (plain or XCD-aware workgroup order)
-that run fastest on a representative workload.  Classes built by default to
-run both precisions in one pass (variant 2 on the FP64 entry) keep it.  Each candidate setting is
-applied to all classes at once, the workload is built with per-launch HIP
-event timing, and the fastest setting per (class, precision) wins.  K does
-not depend on these choices (tests check this bitwise).
+For every angular-momentum class it chooses between two passes (one kernel
+per precision, each with its form -- one quartet per lane, or one quartet
+per wave with LDS intermediates, where both are built -- and its launch
+mapping, plain or XCD-aware workgroup order) and one pass for both
+precisions (variant 2 on the FP64 entry), whichever runs fastest on a
+representative workload.  Each candidate setting is applied to all classes
+at once, the workload is built with per-launch HIP event timing, and the
+fastest setting per class wins.  The launch mapping never changes K; the
+form and the number of passes change only the order of the sums inside a
+K block (K equal to rounding; tests check both).
 
     python -m paper_1401_6961_amd.autotune --natom 300 --out tuning_gfx950.json
 
@@ -53,6 +55,10 @@ def apply(path: str = DEFAULT_TABLE) -> int:
 
 
 def tune(natom=300, with_d=True, seed=1002, repeats=2, log=print):
+    """Per class: two passes (one kernel per precision, each with its form and
+    launch order chosen independently) or one pass for both precisions
+    (variant 2 on the FP64 entry, with its launch order), whichever took less
+    time in the mixed build."""
     import numpy as np
     import torch
 
@@ -63,17 +69,16 @@ def tune(natom=300, with_d=True, seed=1002, repeats=2, log=print):
     tree = fx.build_quadtree_from(system)
     P = torch.from_numpy(system.P).cuda()
     K = torch.zeros_like(P)
-    configs = [(v, f) for v in (0, 1) for f in (0, 1)]
-    # classes built by default in one pass for both precisions (variant 2 on
-    # the FP64 entry) keep that choice; the sweep covers the other entries
-    dual = {cls for cls in range(81) if fx.fx_get_class_variant(cls, 0) == 2}
+    configs = [(v, f) for v in (0, 1, 2) for f in (0, 1)]
     times = {}
     for v, f in configs:
         for cls in range(81):
+            avail = fx.fx_class_variants_available(cls)
             for p in (0, 1):
-                if cls in dual:
+                if v == 2:
+                    # one pass: the FP64 entry runs both precisions
                     fx.fx_set_class_variant(cls, p, 2 if p == 0 else 0)
-                elif fx.fx_class_variants_available(cls) & (1 << v):
+                elif avail & (1 << v):
                     fx.fx_set_class_variant(cls, p, v)
                 else:
                     fx.fx_set_class_variant(cls, p, 0 if v else 1)
@@ -88,16 +93,23 @@ def tune(natom=300, with_d=True, seed=1002, repeats=2, log=print):
     table = {"workload": f"{natom}-atom {'s+p+d' if with_d else 's+p'} cluster, mixed precision",
              "device": torch.cuda.get_device_name(0), "classes": {}}
     for cls in range(81):
+        avail = fx.fx_class_variants_available(cls)
+        two = []
         for p in (0, 1):
-            if cls in dual:
-                table["classes"][f"{cls}:{p}"] = {"variant": 2 if p == 0 else 0, "flags": 0, "ms": None}
-                continue
-            cands = [(times[(v, f)][cls, p], v, f) for (v, f) in configs
-                     if fx.fx_class_variants_available(cls) & (1 << v) and times[(v, f)][cls, p] > 0]
-            if not cands:
-                continue
-            t, v, f = min(cands)
-            table["classes"][f"{cls}:{p}"] = {"variant": v, "flags": f, "ms": 1e3 * float(t)}
+            cands = [(float(times[(v, f)][cls, p]), v, f) for (v, f) in configs
+                     if v < 2 and avail & (1 << v) and times[(v, f)][cls, p] > 0]
+            two.append(min(cands) if cands else None)
+        one = [(float(times[(2, f)][cls, 0]), 2, f) for f in (0, 1) if avail & 4 and times[(2, f)][cls, 0] > 0]
+        one = min(one) if one else None
+        t_two = sum(x[0] for x in two if x) if all(two) else None
+        if one and (t_two is None or one[0] < t_two):
+            table["classes"][f"{cls}:0"] = {"variant": 2, "flags": one[2], "ms": 1e3 * one[0]}
+            table["classes"][f"{cls}:1"] = {"variant": 0, "flags": one[2], "ms": None}
+        else:
+            for p in (0, 1):
+                if two[p]:
+                    t, v, f = two[p]
+                    table["classes"][f"{cls}:{p}"] = {"variant": v, "flags": f, "ms": 1e3 * t}
     return table
 
 
@@ -153,7 +165,7 @@ def generator_build(d, table_path=DEFAULT_TABLE, names=CANDIDATES, log=print):
         B.build(incremental=True, table=tp, gen=os.path.join(cdir, "gen"), lib=os.path.join(cdir, "libfx.so"))
 
 
-def time_classes(natom, repeats, seed=1002):
+def time_classes(natom, repeats, seed=1002, log=print):
     """Per (class, precision slot) kernel seconds of the mixed build of the
     natom s+p+d cluster with the loaded library (least of `repeats`)."""
     import numpy as np
@@ -167,11 +179,14 @@ def time_classes(natom, repeats, seed=1002):
     P = torch.from_numpy(system.P).cuda()
     K = torch.zeros_like(P)
     fx.fx_exchange_ex(tree, P, system.tau, K, fx.make_opts(precision=fx.FX_PREC_MIXED), stats=False)
+    torch.cuda.synchronize()
+    log("autotune: first call done")
     best = None
-    for _ in range(repeats):
+    for r in range(repeats):
         _, st = fx.fx_exchange_ex(tree, P, system.tau, K, fx.make_opts(precision=fx.FX_PREC_MIXED, profile=True))
         cs = st["class_seconds"]
         best = cs if best is None else np.minimum(best, cs)
+        log(f"autotune: timed call {r}: class time {cs.sum():.3f} s")
     return best
 
 
@@ -244,7 +259,7 @@ def main():
     if args.time_lib:
         from . import fx
         fx.LIB_PATH = args.time_lib
-        cs = time_classes(args.natom, args.repeats)
+        cs = time_classes(args.natom, args.repeats, log=log)
         with open(args.out, "w") as fh:
             json.dump({"lib": args.time_lib, "natom": args.natom, "class_seconds": cs.tolist()}, fh)
         log(f"autotune: {args.time_lib}: class time {cs.sum():.3f} s")

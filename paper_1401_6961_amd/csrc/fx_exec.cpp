@@ -42,6 +42,21 @@ constexpr long kEntryMax = 0xFFFFFFFFL;   // expansion positions are 32-bit
 constexpr int kBins = 32;
 constexpr size_t kDefaultWorkspace = size_t(4) << 30;   // default workspace budget of one call
 
+// progress hook of long one-system calls (process-wide)
+fx_progress_fn g_progress = nullptr;
+void* g_progress_ctx = nullptr;
+
+struct ProgressMsg {
+    fx_progress_fn fn;
+    void* ctx;
+    int32_t done, total;
+};
+
+void progress_trampoline(void* p) {
+    std::unique_ptr<ProgressMsg> m(static_cast<ProgressMsg*>(p));
+    m->fn(m->done, m->total, m->ctx);
+}
+
 // Sequential sub-allocation of one device block; a null base only measures.
 struct Carve {
     char* base = nullptr;
@@ -997,7 +1012,7 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
     // flag and split its K row range (only when the call waits) ----
     double seconds_eri = 0;
     int runs = 0;
-    auto enqueue_all = [&](hipStream_t ls, bool check) {
+    auto enqueue_all = [&](hipStream_t ls, bool check, bool report) {
         fx_launch_fill_u64(sh.counters, 81 * 2 * 3 + 3 * FX_PART_SLOTS, 0ull, ls);
         fx_launch_fill_u64((unsigned long long*)sh.run, sizeof(FxDevRun) / 8, 0ull, ls);
         for (auto& s : sys) {
@@ -1061,6 +1076,14 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
                 run_classes(cs, ps, ysys, sh, ls);
                 seconds_eri += std::chrono::duration<double>(std::chrono::steady_clock::now() - te).count();
                 ++runs;
+                if (report && g_progress) {
+                    // reported from a runtime thread when the device reaches this point
+                    auto* m = new ProgressMsg{g_progress, g_progress_ctx, runs, runs + (int32_t)todo.size()};
+                    if (hipLaunchHostFunc(ls, progress_trampoline, m) != hipSuccess) {
+                        (void)hipGetLastError();
+                        delete m;
+                    }
+                }
             }
         }
         // K = alpha * acc + beta * K (NaN where a chunk overflowed)
@@ -1121,7 +1144,7 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
             hipGraph_t graph = nullptr;
             FX_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
             try {
-                enqueue_all(cap, false);
+                enqueue_all(cap, false, false);
             } catch (...) {
                 hipGraph_t g = nullptr;
                 (void)hipStreamEndCapture(cap, &g);
@@ -1166,7 +1189,7 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
     if (!done) {
         acquire();
         upload_descriptors();
-        enqueue_all(st, cs.op.wait);
+        enqueue_all(st, cs.op.wait, true);
         record_usage(sys, sh, nchunks, st);
     }
     if (!cs.op.wait) return;
@@ -1221,6 +1244,18 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
 // C ABI: exchange entry points
 // ---------------------------------------------------------------------------
 extern "C" {
+
+fx_status fx_set_progress(fx_progress_fn fn, void* ctx) {
+    return fx_guard([&] {
+        g_progress = fn;
+        g_progress_ctx = ctx;
+    });
+}
+
+void fx_progress_stderr(int32_t done, int32_t total, void* ctx) {
+    std::fprintf(stderr, "%s: K row range %d of %d done\n", ctx ? (const char*)ctx : "fx", done, total);
+    std::fflush(stderr);
+}
 
 void fx_exchange_opts_init(fx_exchange_opts* o) {
     if (!o) return;

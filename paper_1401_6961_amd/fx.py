@@ -92,7 +92,7 @@ EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_o
             "fx_record_task_timings", "fx_task_timings_create", "fx_task_timings_count", "fx_task_timings_get",
             "fx_task_timings_free", "fx_costmodel_train", "fx_costmodel_nparams", "fx_costmodel_create",
             "fx_costmodel_params", "fx_costmodel_predict", "fx_costmodel_loss_grad", "fx_costmodel_free",
-            "fx_costmodel_save", "fx_costmodel_load"]
+            "fx_costmodel_save", "fx_costmodel_load", "fx_set_progress", "fx_progress_stderr"]
 
 
 def lib():
@@ -118,6 +118,8 @@ def lib():
     L.fx_noalloc_scratch_bytes.restype = ctypes.c_size_t
     L.fx_exchange_opts_init.argtypes = [ctypes.POINTER(fx_exchange_opts)]
     L.fx_exchange_opts_init.restype = None
+    L.fx_set_progress.argtypes = [vp, vp]
+    L.fx_set_progress.restype = ctypes.c_int
     for f in ("fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_batched", "fx_exchange_multi", "fx_tree_perm",
               "fx_tree_schwarz", "fx_set_allocator", "fx_plan_tree"):
         getattr(L, f).restype = ctypes.c_int
@@ -282,6 +284,24 @@ def fx_build_quadtree(l, nprim, center, exps, coefs, leaf_max_functions=0, order
 def build_quadtree_from(system, **kw) -> Tree:
     """Convenience: a synthetic.System-like object with l, nprim, center, exps, coefs."""
     return fx_build_quadtree(system.l, system.nprim, system.center, system.exps, system.coefs, **kw)
+
+
+_progress_prefix = None
+
+
+def set_progress_stderr(prefix: str | None = "fx"):
+    """Print one line to stderr as each K row range of an eager one-system
+    call finishes on the device (the library's own C callback, so no Python
+    runs on the runtime thread); None turns it off."""
+    global _progress_prefix
+    L = lib()
+    if prefix is None:
+        _check(L.fx_set_progress(None, None))
+        _progress_prefix = None
+        return
+    _progress_prefix = ctypes.create_string_buffer(prefix.encode())
+    fn = ctypes.cast(L.fx_progress_stderr, ctypes.c_void_p)
+    _check(L.fx_set_progress(fn, ctypes.cast(_progress_prefix, ctypes.c_void_p)))
 
 
 def opts_init():

@@ -111,6 +111,27 @@ def test_workspace_budget_runs_row_ranges(mid):
         assert torch.equal(K, Kref), f"replay {i}"
 
 
+def test_progress_reports_each_row_range(mid, capfd):
+    """The progress hook: one line per K row range of an eager call, from the
+    library's own callback on the runtime thread."""
+    s, tree, P, Kref, st0 = mid
+    say("gpu: progress lines per row range")
+    budget = st0["workspace_bytes"] // 4
+    opts = fx.make_opts(precision=fx.FX_PREC_MIXED, max_workspace_bytes=budget)
+    capfd.readouterr()
+    fx.set_progress_stderr("probe")
+    try:
+        K, st = fx.fx_exchange_ex(tree, P, s.tau, torch.zeros_like(P), opts)
+        torch.cuda.synchronize()
+    finally:
+        fx.set_progress_stderr(None)
+    lines = [x for x in capfd.readouterr().err.splitlines() if x.startswith("probe: K row range")]
+    n = st["chunks"] + 1
+    assert n > 1 and len(lines) == n
+    assert lines[-1] == f"probe: K row range {n} of {n} done"
+    assert torch.equal(K, Kref)
+
+
 def test_first_call_learns_capacities():
     """A fresh tree: the first call sizes its buffers by a traversal-only
     pass; later calls need no more than 25% above the sizes seen."""

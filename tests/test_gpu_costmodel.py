@@ -1,6 +1,8 @@
 """GPU cost model: the hand-written FP32 forward/backward kernels against the
 FP64 reference, training on the GPU, timing probes, and scheduling that
 never changes K."""
+import os
+
 import numpy as np
 import pytest
 
@@ -113,6 +115,39 @@ def test_learned_model_predicts_unit_time_better_than_bound_only(recorded):
     r2_bound = _r2(coef[0] * (f2[:, 0] + f2[:, 1] + f2[:, 3]) + coef[1], t2)
     say(f"R^2 held-out: mlp {r2_mlp:.3f}  bound-only {r2_bound:.3f}")
     assert r2_mlp > r2_bound
+
+
+@pytest.mark.xfail(strict=False, reason="the learned unit order does not yet beat the bound-only order: "
+                   "4000-atom s+p slab, 5 alternating runs each, 20.52 s learned vs 20.31 s bound-only "
+                   "(K bitwise equal); with one unit per workgroup the order inside a launch has little leverage")
+def test_learned_order_builds_no_slower_than_bound_only():
+    """The shipped model's unit order against the bound-only order on a
+    250-atom s+p+d cluster, 5 alternating runs each: same K bitwise, and the
+    learned order's median no slower."""
+    import time
+    model = fx.CostModel.load(os.path.join(os.path.dirname(fx.__file__), "costmodel_gfx950.fxmlp"))
+    s = synthetic.cluster(250, seed=2250)
+    tree = fx.build_quadtree_from(s)
+    P = torch.from_numpy(s.P).cuda()
+    say("gpu: learned vs bound-only unit order, 250-atom cluster, 5 alternating runs")
+    opts = {"bound": fx.make_opts(precision=fx.FX_PREC_MIXED, schedule=fx.FX_SCHED_BOUND, use_graph=True),
+            "mlp": fx.make_opts(precision=fx.FX_PREC_MIXED, schedule=fx.FX_SCHED_MLP, costmodel=model,
+                                use_graph=True)}
+    Ks = {k: torch.zeros_like(P) for k in opts}
+    for k, o in opts.items():
+        fx.fx_exchange_ex(tree, P, s.tau, Ks[k], o, stats=False)
+    torch.cuda.synchronize()
+    times = {k: [] for k in opts}
+    for r in range(5):
+        for k in (("bound", "mlp") if r % 2 == 0 else ("mlp", "bound")):
+            t0 = time.perf_counter()
+            fx.fx_exchange_ex(tree, P, s.tau, Ks[k], opts[k], stats=False)
+            torch.cuda.synchronize()
+            times[k].append(time.perf_counter() - t0)
+    assert torch.equal(Ks["bound"], Ks["mlp"])
+    med = {k: float(np.median(v)) for k, v in times.items()}
+    say(f"median: learned {med['mlp']:.4f} s, bound-only {med['bound']:.4f} s")
+    assert med["mlp"] <= med["bound"]
 
 
 def test_costmodel_save_load_roundtrip(tmp_path):
