@@ -345,6 +345,18 @@ int64_t fx_xcd_block(int64_t b, int64_t nb);
 /* Bit mask of the variants built for a class (bit v = variant v). */
 int32_t fx_class_variants_available(int32_t cls);
 
+/* Shared screen per (l_a, l_d) group (default off): where every leaf holds at
+ * most one shell of each angular momentum, one kernel per group tests each
+ * entry's nine (l_b, l_c) candidates with the bound of Eq. (8) and the
+ * group's nine class kernels read the outcomes; off, each class kernel tests
+ * its own candidates.  The same quartets are computed in the same order
+ * either way, so K is bitwise the same.  Off by default because it measured
+ * slower (the class kernels' candidate scan is bound by its own loop, not by
+ * the norm gathers this removes).  Process-wide; not thread-safe against
+ * running calls. */
+fx_status fx_set_group_screen(int32_t enabled);
+int32_t fx_get_group_screen(void);
+
 /* Device allocator used for all library memory (NULL, NULL restores
  * hipMallocAsync / hipFreeAsync).  Not thread-safe against running calls. */
 typedef void* (*fx_alloc_fn)(size_t bytes, void* stream, void* ctx);

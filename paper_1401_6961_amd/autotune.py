@@ -54,7 +54,7 @@ def apply(path: str = DEFAULT_TABLE) -> int:
     return n
 
 
-def tune(natom=300, with_d=True, seed=1002, repeats=2, log=print):
+def tune(natom=300, with_d=True, seed=1002, repeats=2, log=print, full=False):
     """Per class: two passes (one kernel per precision, each with its form and
     launch order chosen independently) or one pass for both precisions
     (variant 2 on the FP64 entry, with its launch order), whichever took less
@@ -69,7 +69,10 @@ def tune(natom=300, with_d=True, seed=1002, repeats=2, log=print):
     tree = fx.build_quadtree_from(system)
     P = torch.from_numpy(system.P).cuda()
     K = torch.zeros_like(P)
-    configs = [(v, f) for v in (0, 1, 2) for f in (0, 1)]
+    # the cooperative form and the XCD-aware order lose by large factors at
+    # this size (1000-atom cluster: 151.6 s and 99.2 s against 15.4 s of class
+    # time), so only a full sweep times them
+    configs = [(v, f) for v in (0, 1, 2) for f in (0, 1)] if full else [(0, 0), (2, 0)]
     times = {}
     for v, f in configs:
         for cls in range(81):
@@ -84,10 +87,11 @@ def tune(natom=300, with_d=True, seed=1002, repeats=2, log=print):
                     fx.fx_set_class_variant(cls, p, 0 if v else 1)
                 fx.fx_set_class_launch(cls, p, f)
         best = None
-        for _ in range(repeats):
+        for r in range(repeats):
             _, st = fx.fx_exchange_ex(tree, P, system.tau, K, fx.make_opts(precision=fx.FX_PREC_MIXED, profile=True))
             cs = st["class_seconds"]
             best = cs if best is None else np.minimum(best, cs)
+            log(f"autotune: variant={v} xcd={f} run {r}: {cs.sum():.3f} s")
         times[(v, f)] = best
         log(f"autotune: variant={v} xcd={f} total class time {best.sum():.3f} s")
     table = {"workload": f"{natom}-atom {'s+p+d' if with_d else 's+p'} cluster, mixed precision",
@@ -99,7 +103,8 @@ def tune(natom=300, with_d=True, seed=1002, repeats=2, log=print):
             cands = [(float(times[(v, f)][cls, p]), v, f) for (v, f) in configs
                      if v < 2 and avail & (1 << v) and times[(v, f)][cls, p] > 0]
             two.append(min(cands) if cands else None)
-        one = [(float(times[(2, f)][cls, 0]), 2, f) for f in (0, 1) if avail & 4 and times[(2, f)][cls, 0] > 0]
+        one = [(float(times[(2, f)][cls, 0]), 2, f) for f in (0, 1)
+               if (2, f) in times and avail & 4 and times[(2, f)][cls, 0] > 0]
         one = min(one) if one else None
         t_two = sum(x[0] for x in two if x) if all(two) else None
         if one and (t_two is None or one[0] < t_two):
@@ -248,9 +253,11 @@ def main():
     ap.add_argument("--natom", type=int, default=300)
     ap.add_argument("--sp", action="store_true", help="s+p shells only")
     ap.add_argument("--out", default=DEFAULT_TABLE)
+    ap.add_argument("--base", default=DEFAULT_TABLE, help="table whose generator section the result keeps")
     ap.add_argument("--generator", choices=["build", "measure", "choose"], help="tune the generator's choices")
     ap.add_argument("--dir", default=os.path.join(os.path.dirname(HERE), "_autotune"))
     ap.add_argument("--candidates", default=",".join(CANDIDATES))
+    ap.add_argument("--full", action="store_true", help="also time the cooperative form and the XCD-aware order")
     ap.add_argument("--time-lib", help=argparse.SUPPRESS)
     ap.add_argument("--repeats", type=int, default=2)
     args = ap.parse_args()
@@ -270,10 +277,10 @@ def main():
         return generator_measure(args.dir, args.natom, args.repeats, names=names, log=log)
     if args.generator == "choose":
         return generator_choose(args.dir, names=names, log=log)
-    table = tune(args.natom, with_d=not args.sp, log=lambda m: print(m, flush=True))
-    if os.path.exists(args.out):
+    table = tune(args.natom, with_d=not args.sp, log=lambda m: print(m, flush=True), full=args.full)
+    if os.path.exists(args.base):
         # keep the generator's choices
-        table = dict(json.load(open(args.out)), **table)
+        table = dict(json.load(open(args.base)), **table)
     with open(args.out, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
     print(f"autotune: wrote {len(table['classes'])} entries to {args.out}", flush=True)

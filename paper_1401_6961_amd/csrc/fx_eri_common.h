@@ -213,6 +213,14 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
         if (mode == FX_MODE_MIXED_LO) return beta < thr ? 1 : 0;
         return 1;
     };
+    // a stored screen outcome (0 culled, 1 beta >= thr, 2 beta < thr) as `test` returns it
+    auto category = [&](int cat) -> int {
+        if (cat == 0) return 0;
+        if (DUAL) return cat;
+        if (mode == FX_MODE_MIXED_HI) return cat == 1 ? 1 : 0;
+        if (mode == FX_MODE_MIXED_LO) return cat == 2 ? 1 : 0;
+        return 1;
+    };
     auto push = [&](int cat, int b, int c) {
         const uint64_t m = __ballot(cat == 1);
         if (cat == 1) queue[wave][qn + fx_mbcnt(m)] = make_int2(b, c);
@@ -255,10 +263,16 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
                 constexpr int G = FX_FILL_GROUPS;
                 int2 bcg[G];
                 int bg[G], cg[G], okg[G];
+                uint32_t mw[G];
+                const uint32_t* __restrict__ msk = Sy.mask;
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
                     bcg[g] = make_int2(0, 0);
-                    if (cur + 64 * g + lane < cend) bcg[g] = Sy.bc[cur + 64 * g + lane];
+                    mw[g] = 0;
+                    if (cur + 64 * g + lane < cend) {
+                        bcg[g] = Sy.bc[cur + 64 * g + lane];
+                        if (msk) mw[g] = msk[cur + 64 * g + lane];
+                    }
                 }
 #pragma unroll
                 for (int g = 0; g < G; ++g) {
@@ -268,8 +282,17 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
                         cg[g] = one[bcg[g].y * 3 + LC];
                     }
                 }
+                if (msk) {
+                    // the group's screen (same test, taken once for the nine (l_b, l_c))
 #pragma unroll
-                for (int g = 0; g < G; ++g) okg[g] = (bg[g] >= 0 && cg[g] >= 0) ? test(bg[g], cg[g]) : 0;
+                    for (int g = 0; g < G; ++g) {
+                        const int cat = (int)((mw[g] >> (2 * (3 * LB + LC))) & 3u);
+                        okg[g] = (bg[g] >= 0 && cg[g] >= 0) ? category(cat) : 0;
+                    }
+                } else {
+#pragma unroll
+                    for (int g = 0; g < G; ++g) okg[g] = (bg[g] >= 0 && cg[g] >= 0) ? test(bg[g], cg[g]) : 0;
+                }
 #pragma unroll
                 for (int g = 0; g < G; ++g) push(okg[g], bg[g], cg[g]);
                 cur += 64 * G;

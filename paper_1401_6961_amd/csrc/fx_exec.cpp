@@ -42,6 +42,11 @@ constexpr long kEntryMax = 0xFFFFFFFFL;   // expansion positions are 32-bit
 constexpr int kBins = 32;
 constexpr size_t kDefaultWorkspace = size_t(4) << 30;   // default workspace budget of one call
 
+// shared screen per (l_a, l_d) group where the leaves allow it (process-wide
+// switch, off by default: on the 1000-atom cluster the screen kernels took
+// 0.87 s and the class kernels did not get faster, 15.80 s against 14.91 s)
+int g_group_screen = 0;
+
 // progress hook of long one-system calls (process-wide)
 fx_progress_fn g_progress = nullptr;
 void* g_progress_ctx = nullptr;
@@ -101,6 +106,7 @@ struct SysBufs {
     int2* sorted = nullptr;
     long* cls_off = nullptr;
     unsigned long long* cpart = nullptr;   // partition sums of the chunk being traversed
+    uint32_t* screen = nullptr;            // per leaf entry: the (l_a, l_d) group's screen (one-shell-per-l leaves)
     double* acc[FX_MAX_DENS] = {nullptr, nullptr};
 };
 
@@ -204,6 +210,10 @@ long scan_tiles_max(const Caps& c) {
     return m;
 }
 
+// leaves with at most one shell of each l (and more than one shell): the
+// class kernels of an (l_a, l_d) group read one shared screen of each entry
+bool group_screen(const fx_tree* T) { return T->basis.leaf_one != nullptr && !T->single_shell_leaves; }
+
 void carve_sys(Carve& cv, Sys& s, int ndens, bool own_acc) {
     const fx_tree* T = s.T;
     const Caps& c = s.caps;
@@ -236,6 +246,7 @@ void carve_sys(Carve& cv, Sys& s, int ndens, bool own_acc) {
         b.cls_off = cv.take<long>(10 * c.items);
     }
     b.cpart = cv.take<unsigned long long>(3 * FX_PART_SLOTS);
+    if (group_screen(T)) b.screen = cv.take<uint32_t>(c.e_leaf);
     for (int j = 0; j < ndens; ++j) b.acc[j] = own_acc ? cv.take<double>((size_t)T->n * T->n) : nullptr;
 }
 
@@ -365,7 +376,7 @@ void traverse(Sys& s, double tau, double tau_ovlp, bool allow_sym, bool count_ro
 
 // The system as the class kernels see it (host-side description: every
 // pointer is fixed once the call's block is laid out).
-FxSys describe(const Sys& s, int ndens) {
+FxSys describe(const Sys& s, int ndens, bool screen) {
     const fx_tree* T = s.T;
     const SysBufs& b = s.b;
     const int lv = (int)T->levels.size() - 1;
@@ -380,6 +391,7 @@ FxSys describe(const Sys& s, int ndens) {
     Y.bc_off = b.off[lv & 1];
     Y.bc = T->single_shell_leaves ? b.sorted : b.leafbc;
     Y.cls_off = T->single_shell_leaves ? b.cls_off : nullptr;
+    Y.mask = screen ? b.screen : nullptr;
     Y.cnt = s.cnt;
     return Y;
 }
@@ -464,6 +476,14 @@ void run_classes(CallState& cs, std::vector<Sys*>& sys, std::vector<FxSys>& ysys
                 args.unit_sys = nullptr;
                 args.sys = nullptr;
                 args.one = ysys[0];
+                if (ysys[0].mask) {
+                    // the group's nine class kernels read this screen
+                    const Sys& s0 = *sys[0];
+                    const int lv = (int)s0.T->levels.size() - 1;
+                    fx_launch_screen_group(s0.b.ad[lv & 1], s0.b.off[lv & 1], s0.b.leafbc, s0.cnt, lv, s0.caps.items,
+                                           s0.T->basis, s0.b.Pn, la, ld, cs.tau, op.o.fp32_threshold, op.o.tau_ovlp,
+                                           s0.b.screen, st);
+                }
             }
             for (int lb = 0; lb <= lmax; ++lb)
                 for (int lc = 0; lc <= lmax; ++lc) {
@@ -580,6 +600,7 @@ std::vector<uint64_t> graph_key(const fx_tree* const* trees, const double* const
     k.push_back((uint64_t)count);
     k.push_back((uint64_t)ndens);
     k.push_back((uint64_t)nchunks);
+    k.push_back((uint64_t)g_group_screen);
     for (int i = 0; i < count; ++i) {
         k.push_back(trees[i]->id);
         for (int j = 0; j < ndens; ++j) {
@@ -1023,7 +1044,9 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
             density_norms(s, ndens, allow_sym, ls);
         }
         std::vector<FxSys> ysys(count);
-        for (int i = 0; i < count; ++i) ysys[i] = describe(sys[i], ndens);
+        // one shared screen per (l_a, l_d) group: one system, shell-level screening
+        const bool screen = g_group_screen && count == 1 && o.leaf_screen == FX_LEAF_SHELL && group_screen(sys[0].T);
+        for (int i = 0; i < count; ++i) ysys[i] = describe(sys[i], ndens, screen);
         runs = 0;
         if (count > 1) {
             for (int i = 0; i < count; ++i) {
@@ -1103,7 +1126,7 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
         for (int i = 0; i < count; ++i) {
             if (!own_acc)
                 for (int j = 0; j < ndens; ++j) sys[i].b.acc[j] = sys[i].K[j];
-            ys[i] = describe(sys[i], ndens);
+            ys[i] = describe(sys[i], ndens, false);
         }
         FX_HIP(hipMemcpyAsync(sh.dsys, ys.data(), sizeof(FxSys) * count, hipMemcpyHostToDevice, st));
         FX_HIP(hipStreamSynchronize(st));
@@ -1244,6 +1267,12 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
 // C ABI: exchange entry points
 // ---------------------------------------------------------------------------
 extern "C" {
+
+fx_status fx_set_group_screen(int32_t enabled) {
+    return fx_guard([&] { g_group_screen = enabled ? 1 : 0; });
+}
+
+int32_t fx_get_group_screen(void) { return g_group_screen; }
 
 fx_status fx_set_progress(fx_progress_fn fn, void* ctx) {
     return fx_guard([&] {

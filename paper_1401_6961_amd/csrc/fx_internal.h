@@ -84,6 +84,9 @@ struct FxSys {
     const long* bc_off;               // per leaf item: offsets into bc
     const int2* bc;                   // (B, C) leaf nodes
     const long* cls_off;              // single-shell leaves: per item 10 class offsets, else null
+    const uint32_t* mask;             // leaves with at most one shell of each l: per leaf entry, the screen of
+                                      // the (l_a, l_d) group being launched, 2 bits per (l_b, l_c) at bit
+                                      // 2 (3 l_b + l_c): 0 culled, 1 beta >= thr, 2 beta < thr; or null
     double* acc[FX_MAX_DENS];         // K accumulator of each density (n x n, caller order)
     const FxDevCounts* cnt;           // sizes; cnt->sym = 1: only units a <= d (tree order) exist and each
                                       // writes K_ad and K_da

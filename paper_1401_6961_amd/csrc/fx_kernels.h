@@ -70,6 +70,9 @@ void fx_launch_expand_write(const FxLevelArgs& L, long n_max, const uint8_t* mas
                             const long* adpos, int2* bc_next, int* parent_next, hipStream_t st);
 void fx_launch_unit_count(const int2* items, const FxDevCounts* cnt, int lv, long cap, const int* leaf_lofs,
                           const int* leaf_lsh, int* out, hipStream_t st);
+void fx_launch_screen_group(const int2* items, const long* item_off, const int2* bc, const FxDevCounts* cnt, int lv,
+                            long cap, const FxDevBasis& B, const double* Pn, int la, int ld, double tau, double thr,
+                            double tau_ovlp, uint32_t* mask, hipStream_t st);
 void fx_launch_leaf_rows(const int2* items, const long* off, const FxDevCounts* cnt, int lv, long cap,
                          unsigned long long* rows, hipStream_t st);
 void fx_launch_unit_bounds(const long* upos, long cap, FxDevCounts* cnt, hipStream_t st);

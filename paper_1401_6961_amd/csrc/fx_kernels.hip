@@ -717,6 +717,67 @@ void fx_launch_unit_count(const int2* items, const FxDevCounts* cnt, int lv, lon
                        leaf_lsh, out);
 }
 
+// Screen of one (l_a, l_d) group, for leaves that hold at most one shell of
+// each angular momentum: a leaf item (A, D) then has one K-block unit (a, d)
+// in the group and each of its (B, C) entries one candidate (b, c) per
+// (l_b, l_c).  The nine candidates of an entry are tested here once with the
+// shell-level metric query of Eq. (8) (and the overlap criterion of
+// Eqs. (3)-(4) when on), in exactly the arithmetic the class kernels use, and
+// the outcomes are stored as 2 bits per (l_b, l_c); the group's nine class
+// kernels read them instead of gathering the norms again.  The 3x3 block of
+// ||P_bc|| an entry needs lies in three rows of the norm table, so this pass
+// reads each row segment once for the group.  One wave per leaf item.
+__global__ __launch_bounds__(256) void fx_k_screen_group(const int2* __restrict__ items,
+                                                         const long* __restrict__ item_off,
+                                                         const int2* __restrict__ bc, const FxDevCounts* cnt, int lv,
+                                                         long cap, FxDevBasis B, const double* __restrict__ Pn, int la,
+                                                         int ld, double tau, double thr, double tau_ovlp,
+                                                         uint32_t* __restrict__ mask) {
+    const long nitems = cnt->nad[lv] < cap ? cnt->nad[lv] : cap;
+    const int lane = threadIdx.x & 63;
+    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
+    const int S = B.nshell;
+    const int* __restrict__ one = B.leaf_one;
+    const bool ovlp = tau_ovlp > 0.0;
+    for (long it = wave; it < nitems; it += nwaves) {
+        const int2 ad = items[it];
+        const int a = one[ad.x * 3 + la], d = one[ad.y * 3 + ld];
+        if (a < 0 || d < 0) continue;
+        const double* __restrict__ Qa = B.Qn + (long)a * S;
+        const double* __restrict__ Qd = B.Qn + (long)d * S;
+        const double* __restrict__ Sa = B.Sm + (long)a * S;
+        const double* __restrict__ Sd = B.Sm + (long)d * S;
+        const long e1 = item_off[it + 1];
+        for (long e = item_off[it] + lane; e < e1; e += 64) {
+            const int2 x = bc[e];
+            uint32_t m = 0;
+#pragma unroll
+            for (int lb = 0; lb < 3; ++lb) {
+                const int b = one[x.x * 3 + lb];
+                if (b < 0) continue;
+#pragma unroll
+                for (int lc = 0; lc < 3; ++lc) {
+                    const int c = one[x.y * 3 + lc];
+                    if (c < 0) continue;
+                    const double beta = (Qa[b] * Qd[c]) * Pn[(long)b * S + c];
+                    uint32_t cat = 0;
+                    if (beta > tau && !(ovlp && !(Sa[b] >= tau_ovlp && Sd[c] >= tau_ovlp))) cat = beta < thr ? 2u : 1u;
+                    m |= cat << (2 * (3 * lb + lc));
+                }
+            }
+            mask[e] = m;
+        }
+    }
+}
+
+void fx_launch_screen_group(const int2* items, const long* item_off, const int2* bc, const FxDevCounts* cnt, int lv,
+                            long cap, const FxDevBasis& B, const double* Pn, int la, int ld, double tau, double thr,
+                            double tau_ovlp, uint32_t* mask, hipStream_t st) {
+    hipLaunchKernelGGL(fx_k_screen_group, dim3(fx_grid_for(64 * cap, 256)), dim3(256), 0, st, items, item_off, bc,
+                       cnt, lv, cap, B, Pn, la, ld, tau, thr, tau_ovlp, mask);
+}
+
 // Leaf entries per leaf row: for every leaf item (A, D), its entry count is
 // added to row A.  Used to cut K into row ranges of similar size.
 __global__ __launch_bounds__(256) void fx_k_leaf_rows(const int2* __restrict__ items, const long* __restrict__ off,

@@ -92,7 +92,8 @@ EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_o
             "fx_record_task_timings", "fx_task_timings_create", "fx_task_timings_count", "fx_task_timings_get",
             "fx_task_timings_free", "fx_costmodel_train", "fx_costmodel_nparams", "fx_costmodel_create",
             "fx_costmodel_params", "fx_costmodel_predict", "fx_costmodel_loss_grad", "fx_costmodel_free",
-            "fx_costmodel_save", "fx_costmodel_load", "fx_set_progress", "fx_progress_stderr"]
+            "fx_costmodel_save", "fx_costmodel_load", "fx_set_progress", "fx_progress_stderr",
+            "fx_set_group_screen", "fx_get_group_screen"]
 
 
 def lib():
@@ -120,6 +121,10 @@ def lib():
     L.fx_exchange_opts_init.restype = None
     L.fx_set_progress.argtypes = [vp, vp]
     L.fx_set_progress.restype = ctypes.c_int
+    L.fx_set_group_screen.argtypes = [i32]
+    L.fx_set_group_screen.restype = ctypes.c_int
+    L.fx_get_group_screen.argtypes = []
+    L.fx_get_group_screen.restype = i32
     for f in ("fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_batched", "fx_exchange_multi", "fx_tree_perm",
               "fx_tree_schwarz", "fx_set_allocator", "fx_plan_tree"):
         getattr(L, f).restype = ctypes.c_int
@@ -284,6 +289,16 @@ def fx_build_quadtree(l, nprim, center, exps, coefs, leaf_max_functions=0, order
 def build_quadtree_from(system, **kw) -> Tree:
     """Convenience: a synthetic.System-like object with l, nprim, center, exps, coefs."""
     return fx_build_quadtree(system.l, system.nprim, system.center, system.exps, system.coefs, **kw)
+
+
+def set_group_screen(enabled: bool) -> None:
+    """Process-wide: one shared screen per (l_a, l_d) group, or a screen in
+    every class kernel (default); K is bitwise the same."""
+    _check(lib().fx_set_group_screen(int(bool(enabled))))
+
+
+def get_group_screen() -> bool:
+    return bool(lib().fx_get_group_screen())
 
 
 _progress_prefix = None

@@ -132,6 +132,28 @@ def test_progress_reports_each_row_range(mid, capfd):
     assert torch.equal(K, Kref)
 
 
+def test_group_screen_gives_the_same_K(mid):
+    """One shared screen per (l_a, l_d) group against a screen in every class
+    kernel (the default): the same quartets in the same order, so K is
+    bitwise the same (mixed and FP64, eager and replayed)."""
+    s, tree, P, Kref, st0 = mid
+    say("gpu: shared group screen on / off")
+    assert not fx.get_group_screen()
+    K64, st64 = fx.fx_exchange_ex(tree, P, s.tau, torch.zeros_like(P))
+    fx.set_group_screen(True)
+    try:
+        Kon, st = fx.fx_exchange_ex(tree, P, s.tau, torch.zeros_like(P), fx.make_opts(precision=fx.FX_PREC_MIXED))
+        K64on, st64on = fx.fx_exchange_ex(tree, P, s.tau, torch.zeros_like(P))
+        Kg = torch.zeros_like(P)
+        fx.fx_exchange_ex(tree, P, s.tau, Kg, fx.make_opts(precision=fx.FX_PREC_MIXED, use_graph=True), stats=False)
+        torch.cuda.synchronize()
+    finally:
+        fx.set_group_screen(False)
+    assert torch.equal(Kon, Kref) and torch.equal(Kg, Kref) and torch.equal(K64on, K64)
+    assert np.array_equal(st["class_prec_quartets"], st0["class_prec_quartets"])
+    assert st64on["quartets"] == st64["quartets"]
+
+
 def test_first_call_learns_capacities():
     """A fresh tree: the first call sizes its buffers by a traversal-only
     pass; later calls need no more than 25% above the sizes seen."""
