@@ -138,11 +138,13 @@ typedef struct fx_exchange_opts {
                                    (or, in the traversal, of blocks) all of whose functions overlap less
                                    than tau_ovlp contributes nothing.  Unlike tau this drops work the
                                    metric query would keep, without a bound on the change of K. */
-    int64_t max_workspace_bytes; /* device workspace of a one-system call, in bytes: 0 = 4 GiB (default),
-                                   < 0 = no limit but 80% of the free device memory.  A traversal that needs
-                                   more is run over K row ranges (at leaf-block boundaries) one after
-                                   another; K does not depend on it.  Below what one leaf row of K needs
-                                   the call takes that much (stats.workspace_bytes tells). */
+    int64_t max_workspace_bytes; /* device workspace of a one-system call, in bytes: 0 = the default, 4 GiB
+                                   or what 64 K row ranges need if that is more (within 80% of the free
+                                   device memory); < 0 = no limit but 80% of the free device memory.  A
+                                   traversal that needs more is run over K row ranges (at leaf-block
+                                   boundaries) one after another; K does not depend on it.  Below what one
+                                   leaf row of K needs the call takes that much (stats.workspace_bytes
+                                   tells). */
 } fx_exchange_opts;
 
 /* Fill *o with the defaults documented above. */

@@ -150,15 +150,17 @@ __device__ __forceinline__ double fx_comp_factor(int l, int k) {
 // DUAL (mixed precision in one pass): each candidate is screened once and
 // queued for the FP64 routine `fn` (beta >= thr) or the FP32 routine `fn2`
 // (beta < thr); both accumulate into the same FP64 K block.
-// Candidate queue of one wave in LDS: a fill step screens up to FX_FILL_GROUPS
-// groups of 64 entries and adds their survivors to a queue holding at most
-// 63; a batch takes 64 from its front.
-constexpr int FX_FILL_GROUPS = 3;
-constexpr int FX_QCAP = 64 * (FX_FILL_GROUPS + 1);
+// Candidate queue of one wave in LDS: a fill step screens up to G groups of
+// 64 entries (G per kernel, from the generator's table; more groups overlap
+// more gathers but cost registers) and adds their survivors to a queue
+// holding at most 63; a batch takes 64 from its front.
+constexpr int FX_FILL_GROUPS = 3;   // default G
+template <int G>
+constexpr int fx_qcap() { return 64 * (G + 1); }
 
-template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, int NDENS, bool DUAL, typename Fn, typename Fn2>
+template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, int NDENS, bool DUAL, int G, typename Fn, typename Fn2>
 __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 fn2, long slot_unit, int wave,
-                                              int2 (*queue)[FX_QCAP], int2 (*queue2)[FX_QCAP]) {
+                                              int2 (*queue)[fx_qcap<G>()], int2 (*queue2)[fx_qcap<G>()]) {
     static_assert(!COOP || NDENS == 1, "the one-quartet-per-wave form contracts one density");
     static_assert(!COOP || !DUAL, "the one-quartet-per-wave form runs one precision");
     constexpr int NA = fx_ncart(LA), ND = fx_ncart(LD);
@@ -257,10 +259,9 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
                 push(ok, b, c);
                 cur += 64;
             } else if (one) {
-                // FX_FILL_GROUPS groups of 64 entries per step: their gathers
+                // G groups of 64 entries per step: their gathers
                 // overlap; pushed in entry order
                 if (cur >= cend) break;
-                constexpr int G = FX_FILL_GROUPS;
                 int2 bcg[G];
                 int bg[G], cg[G], okg[G];
                 uint32_t mw[G];
@@ -334,7 +335,7 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
         // neither queue full: the candidates are exhausted, drain both
         const bool drain = qn < 64 && qn2 < 64;
         // evaluate one batch of a queue (the only call sites of the routines)
-        auto batch = [&](int2 (*qq)[FX_QCAP], int& n, auto& f, long& cnt, long& np) {
+        auto batch = [&](int2 (*qq)[fx_qcap<G>()], int& n, auto& f, long& cnt, long& np) {
             const int nbatch = n < 64 ? n : 64;
             if (COOP) {
                 // the whole wave evaluates the queued quartets one after another
@@ -345,14 +346,14 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
             }
             cnt += nbatch;
             fx_wave_sync();
-            // move the rest (at most FX_QCAP - 65) to the front; lane i reads
+            // move the rest (at most 64 G - 1) to the front; lane i reads
             // slots 64 (k + 1) + i and writes slots 64 k + i, so no lane
             // overwrites a slot another lane still has to read
-            int2 t[FX_FILL_GROUPS];
+            int2 t[G];
 #pragma unroll
-            for (int k = 0; k < FX_FILL_GROUPS; ++k) t[k] = qq[wave][64 * (k + 1) + lane];
+            for (int k = 0; k < G; ++k) t[k] = qq[wave][64 * (k + 1) + lane];
 #pragma unroll
-            for (int k = 0; k < FX_FILL_GROUPS; ++k) qq[wave][64 * k + lane] = t[k];
+            for (int k = 0; k < G; ++k) qq[wave][64 * k + lane] = t[k];
             n -= nbatch;
             fx_wave_sync();
         };
@@ -407,17 +408,17 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
 // of workgroups (fx_xcd_remap) so that neighbouring units -- which share
 // density and pair data -- run on one XCD and its L2.  K does not depend on
 // the mapping.
-template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, int NDENS, bool DUAL = false, typename Fn,
-          typename Fn2>
+template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, int NDENS, bool DUAL = false,
+          int G = FX_FILL_GROUPS, typename Fn, typename Fn2>
 __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn, Fn2 fn2) {
-    __shared__ int2 queue[WAVES][FX_QCAP];
-    __shared__ int2 queue2[DUAL ? WAVES : 1][FX_QCAP];
+    __shared__ int2 queue[WAVES][fx_qcap<G>()];
+    __shared__ int2 queue2[DUAL ? WAVES : 1][fx_qcap<G>()];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     long blk = blockIdx.x;
     if (A.flags & FX_LAUNCH_XCD) blk = fx_xcd_remap(blk, gridDim.x);
     const long slot_unit = blk * WAVES + wave;
     if (slot_unit >= __builtin_amdgcn_readfirstlane((int)(A.ulh[1] - A.ulh[0]))) return;
-    fx_class_unit<LA, LB, LC, LD, COOP, WAVES, NDENS, DUAL>(A, fn, fn2, slot_unit, wave, queue, queue2);
+    fx_class_unit<LA, LB, LC, LD, COOP, WAVES, NDENS, DUAL, G>(A, fn, fn2, slot_unit, wave, queue, queue2);
 }
 
 // Thread variant: one quartet per lane.
@@ -430,6 +431,17 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn, Fn2 f
 #ifndef FX_THREAD_MIN_WAVES_f32
 #define FX_THREAD_MIN_WAVES_f32 1
 #endif
+// FX_FILL_GROUPS_f64 / _f32 / _mix (set per class by the generator): entry
+// groups per fill step of the candidate scan.
+#ifndef FX_FILL_GROUPS_f64
+#define FX_FILL_GROUPS_f64 FX_FILL_GROUPS
+#endif
+#ifndef FX_FILL_GROUPS_f32
+#define FX_FILL_GROUPS_f32 FX_FILL_GROUPS
+#endif
+#ifndef FX_FILL_GROUPS_mix
+#define FX_FILL_GROUPS_mix FX_FILL_GROUPS
+#endif
 // Instantiated for one and for two densities (FxClassArgs::ndens).
 #define FX_THREAD_KERNEL(la, lb, lc, ld, cls, prec)                                                     \
     template <int NDENS>                                                                                 \
@@ -439,7 +451,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn, Fn2 f
                     const FxDevBasis& B, const double* bt, const double* const* P, long n, double* k, int) { \
             eri_##cls##_##prec<NDENS>(ra, rb, rc, rd, B, bt, P, n, k);                                   \
         };                                                                                               \
-        fx_class_body<la, lb, lc, ld, false, FX_CLASS_WAVES, NDENS>(A, f, f);                            \
+        fx_class_body<la, lb, lc, ld, false, FX_CLASS_WAVES, NDENS, false, FX_FILL_GROUPS_##prec>(A, f, f); \
     }
 
 // Mixed precision in one pass: each candidate screened once, evaluated by the
@@ -458,7 +470,7 @@ __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn, Fn2 f
                       const FxDevBasis& B, const double* bt, const double* const* P, long n, double* k, int) { \
             eri_##cls##_f32<1>(ra, rb, rc, rd, B, bt, P, n, k);                                          \
         };                                                                                               \
-        fx_class_body<la, lb, lc, ld, false, FX_CLASS_WAVES, 1, true>(A, f64, f32);                      \
+        fx_class_body<la, lb, lc, ld, false, FX_CLASS_WAVES, 1, true, FX_FILL_GROUPS_mix>(A, f64, f32);  \
     }
 #define FX_LAUNCH_DUAL(cls)                                                                             \
     hipLaunchKernelGGL(fx_k_##cls##_mix, dim3((A.nbound + FX_CLASS_WAVES - 1) / FX_CLASS_WAVES),         \

@@ -41,6 +41,7 @@ constexpr size_t kAlign = 256;
 constexpr long kEntryMax = 0xFFFFFFFFL;   // expansion positions are 32-bit
 constexpr int kBins = 32;
 constexpr size_t kDefaultWorkspace = size_t(4) << 30;   // default workspace budget of one call
+constexpr int kDefaultMaxRanges = 64;                     // ... unless that takes more K row ranges
 
 // shared screen per (l_a, l_d) group where the leaves allow it (process-wide
 // switch, off by default: on the 1000-atom cluster the screen kernels took
@@ -877,10 +878,79 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
     } else {
         bool learn = false;
         for (auto& s : sys) learn |= o.max_frontier_entries == 0 && s.T->hint.e_in == 0;
-        if (learn) {
+        if (learn && count == 1) {
             // first call on a tree: traverse only, growing the capacity of the
-            // level that overflowed until every level fits; the hint is then
-            // the exact sizes seen (and, for one system, the leaf entries per row)
+            // level that overflowed until every level fits, over K row ranges
+            // when one pass would need more than 32-bit positions or more memory
+            // than the device holds; the hint is then the sizes seen, summed over
+            // the ranges, and the leaf entries per row
+            Sys& s = sys[0];
+            const fx_tree* T = s.T;
+            FxSizeHint& h = T->hint;
+            const int nl = (int)T->levels.size();
+            const int lv = nl - 1;
+            const int nleaf = (int)T->levels.back().sL.size();
+            long want_in = 1L << 16, want_leaf = 1L << 18;
+            int lc = 1;
+            bool learned = false;
+            for (int attempt = 0; attempt < 128 && !learned; ++attempt) {
+                const Ranges rr = lc > 1 ? row_ranges(T, lc) : whole_rows(T);
+                s.caps = make_caps(T, want_in, want_leaf, rr);
+                const size_t avail = free_device_bytes();
+                if (avail > 0 && layout(nullptr) > avail / 10 * 8 && lc < nleaf) {
+                    lc = std::min(nleaf, 2 * lc);
+                    want_in = std::max(1L << 16, want_in / 2);
+                    want_leaf = std::max(1L << 18, want_leaf / 2);
+                    continue;
+                }
+                acquire();
+                fx_launch_fill_u64((unsigned long long*)sh.run, sizeof(FxDevRun) / 8, 0ull, st);
+                fx_launch_fill_u64(sh.rows, nleaf, 0ull, st);
+                density_norms(s, ndens, allow_sym, st);
+                std::vector<FxDevCounts> hc(rr.size());
+                for (size_t r = 0; r < rr.size(); ++r) {
+                    s.a_lo = rr[r].first;
+                    s.a_hi = rr[r].second;
+                    traverse(s, tau, o.tau_ovlp, allow_sym, r == 0, st, sh);
+                    fx_launch_leaf_rows(s.b.ad[lv & 1], s.b.off[lv & 1], s.cnt, lv, s.caps.items, sh.rows, st);
+                    FX_HIP(hipMemcpyAsync(&hc[r], s.cnt, sizeof(FxDevCounts), hipMemcpyDeviceToHost, st));
+                }
+                std::vector<unsigned long long> rows(nleaf, 0ull);
+                FX_HIP(hipMemcpyAsync(rows.data(), sh.rows, sizeof(unsigned long long) * nleaf, hipMemcpyDeviceToHost,
+                                      st));
+                FX_HIP(hipStreamSynchronize(st));
+                release();
+                bool again = false, split = false;
+                for (const auto& c : hc) {
+                    if (!c.overflow) continue;
+                    if (c.need > kEntryMax) split = true;
+                    else if (c.need_level == lv) want_leaf = std::max(want_leaf, c.need);
+                    else want_in = std::max(want_in, c.need);
+                    again = true;
+                }
+                if (split) {
+                    // more entries than 32-bit positions index in one range
+                    if (lc >= nleaf) fx_fail(FX_ERR_OOM, "one row of leaf blocks exceeds 2^32 traversal entries");
+                    lc = std::min(nleaf, 2 * lc);
+                    continue;
+                }
+                if (again) continue;
+                long ein = 1, eleaf = 0;
+                for (int k = 0; k < nl; ++k) {
+                    long sum = 0;
+                    for (const auto& c : hc) sum += c.ne[k];
+                    if (k < lv) ein = std::max(ein, sum);
+                    else eleaf = sum;
+                }
+                h.e_in = ein;
+                h.e_leaf = std::max(1L, eleaf);
+                h.leaf_rows.assign(rows.begin(), rows.end());
+                learned = true;
+            }
+            if (!learned) fx_fail(FX_ERR_OOM, "the traversal did not fit the device in any split of K rows");
+        } else if (learn) {
+            // first call on a batch: each system's whole traversal, growing the
+            // capacity of the level that overflowed until every level fits
             std::vector<long> want_in(count, 1L << 16), want_leaf(count, 1L << 18);
             for (int attempt = 0; attempt < 64; ++attempt) {
                 for (int i = 0; i < count; ++i)
@@ -892,16 +962,6 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
                     s.a_lo = 0;
                     s.a_hi = s.T->S;
                     traverse(s, tau, o.tau_ovlp, allow_sym, true, st, sh);
-                }
-                const int nleaf0 = (int)sys[0].T->levels.back().sL.size();
-                std::vector<unsigned long long> rows(nleaf0, 0ull);
-                if (count == 1) {
-                    const int lv = (int)sys[0].T->levels.size() - 1;
-                    fx_launch_fill_u64(sh.rows, nleaf0, 0ull, st);
-                    fx_launch_leaf_rows(sys[0].b.ad[lv & 1], sys[0].b.off[lv & 1], sys[0].cnt, lv,
-                                        sys[0].caps.items, sh.rows, st);
-                    FX_HIP(hipMemcpyAsync(rows.data(), sh.rows, sizeof(unsigned long long) * nleaf0,
-                                          hipMemcpyDeviceToHost, st));
                 }
                 std::vector<FxDevCounts> hc(count);
                 FX_HIP(hipMemcpyAsync(hc.data(), sh.cnts, sizeof(FxDevCounts) * count, hipMemcpyDeviceToHost, st));
@@ -915,24 +975,14 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
                     for (int k = 0; k + 1 < nl; ++k) ein = std::max(ein, hc[i].ne[k]);
                     if (hc[i].overflow) {
                         const long need = hc[i].need;
-                        const bool leaf = hc[i].need_level == nl - 1;
-                        if (need > kEntryMax) {
-                            // more than 32-bit positions index: the total is known (the scan
-                            // counts every child); row ranges share it
-                            if (count > 1) fx_fail(FX_ERR_OOM, "a batched system exceeds the frontier capacity");
-                            if (!leaf) fx_fail(FX_ERR_OOM, "an inner traversal level exceeds 2^32 entries");
-                            h.e_in = ein;
-                            h.e_leaf = need;
-                            continue;
-                        }
-                        if (leaf) want_leaf[i] = std::max(want_leaf[i], need);
+                        if (need > kEntryMax) fx_fail(FX_ERR_OOM, "a batched system exceeds the frontier capacity");
+                        if (hc[i].need_level == nl - 1) want_leaf[i] = std::max(want_leaf[i], need);
                         else want_in[i] = std::max(want_in[i], need);
                         again = true;
                         continue;
                     }
                     h.e_in = ein;
                     h.e_leaf = std::max(1L, hc[i].ne[nl - 1]);
-                    if (count == 1) h.leaf_rows.assign(rows.begin(), rows.end());
                 }
                 if (!again) break;
             }
@@ -979,7 +1029,15 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
                 // a budget below the part that does not shrink with more ranges
                 // (densities' norms, accumulators) is met as closely as is useful
                 const size_t floor_bytes = bytes_at(nleaf);
-                const size_t limit = std::max(budget, floor_bytes + floor_bytes / 4);
+                size_t limit = std::max(budget, floor_bytes + floor_bytes / 4);
+                if (o.max_workspace_bytes == 0 && nleaf > kDefaultMaxRanges) {
+                    // the default budget gives way to launch size: more ranges than this
+                    // leave class launches too small to fill the device, so large systems
+                    // take what 64 ranges need while 80% of the free memory holds it
+                    const size_t at_max = bytes_at(kDefaultMaxRanges);
+                    const size_t cap = avail > 0 ? avail / 10 * 8 : SIZE_MAX;
+                    if (at_max > limit) limit = std::min(at_max, std::max(limit, cap));
+                }
                 nchunks = fewest(nchunks, limit);
                 // the entries of each of these ranges, measured once (traversal only)
                 for (int round = 0; round < 3 && nchunks > 1 && h.range_chunks != nchunks; ++round) {

@@ -834,23 +834,24 @@ COOP_MIN, THREAD_MAX = 100, 1 << 30
 # routine -- "register" (gen_class), "staged" or "folded" (gen_class_staged
 # without / with the folded ket HRR), "chunked" (gen_class_chunked, with
 # "chunks" and "xreg") --, whether staged forms evaluate two primitive
-# quartets per pass ("paired"), and the waves per SIMD that the register
-# allocation must allow ("waves"); a "<class>:mix" entry builds the class's
+# quartets per pass ("paired"), the waves per SIMD that the register
+# allocation must allow ("waves"), and the entry groups per fill step of the
+# candidate scan ("groups", default 3); a "<class>:mix" entry builds the class's
 # mixed-precision kernel that screens each candidate once and runs both
 # precisions in one pass, with its own "waves".  Without a table every
 # kernel is the register form at one wave, in two passes.
 TABLE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tuning_gfx950.json")
 
 STAGED, FOLD, UNPAIRED, DUAL = set(), set(), set(), set()
-MIN_WAVES, CHUNKS = {}, {}
+MIN_WAVES, CHUNKS, GROUPS = {}, {}, {}
 XREG = set()
 
 
 def load_choices(path=TABLE):
     """Fill the choice sets from a tuning table (empty sets without one)."""
-    global STAGED, FOLD, UNPAIRED, DUAL, MIN_WAVES, CHUNKS, XREG
+    global STAGED, FOLD, UNPAIRED, DUAL, MIN_WAVES, CHUNKS, XREG, GROUPS
     STAGED, FOLD, UNPAIRED, DUAL = set(), set(), set(), set()
-    MIN_WAVES, CHUNKS, XREG = {}, {}, set()
+    MIN_WAVES, CHUNKS, XREG, GROUPS = {}, {}, set(), {}
     if not os.path.exists(path):
         return
     import json
@@ -859,6 +860,8 @@ def load_choices(path=TABLE):
         cls, prec = key.split(":")
         if e.get("waves", 1) > 1:
             MIN_WAVES[(cls, prec)] = int(e["waves"])
+        if e.get("groups", 3) != 3:
+            GROUPS[(cls, prec)] = int(e["groups"])
         if prec == "mix":
             DUAL.add(cls)
             continue
@@ -912,7 +915,12 @@ def main(outdir):
         for prec in ("f64", "f32", "mix"):
             mw = MIN_WAVES.get((cls, prec), 1)
             if mw > 1:
+                src.append(f"#undef FX_THREAD_MIN_WAVES_{prec}")
                 src.append(f"#define FX_THREAD_MIN_WAVES_{prec} {mw}")
+            g = GROUPS.get((cls, prec), 3)
+            if g != 3:
+                src.append(f"#undef FX_FILL_GROUPS_{prec}")
+                src.append(f"#define FX_FILL_GROUPS_{prec} {g}")
         src.append(f'FX_DEFINE_CLASS_KERNELS_{kind}({la}, {lb}, {lc}, {ld}, {cls})')
         path = os.path.join(outdir, f"eri_{cls}.hip")
         new = "\n".join(src) + "\n"
