@@ -467,6 +467,7 @@ def bench_regimes(args, log):
     import paper_1401_6961_amd as fx
     sizes = (125, 250, 500, 1000)
     regimes = ((1e-8, 0.0), (1e-8, 1e-11), (1e-10, 1e-13))
+    fx.set_progress_stderr("bench: regimes")
     series = {}
     for tau, tov in regimes:
         rows = []
@@ -497,6 +498,7 @@ def bench_chain(args, log):
     import torch
     import synthetic
     import paper_1401_6961_amd as fx
+    fx.set_progress_stderr("bench: chain")
     rows = []
     for natom in (50, 100, 200, 400, 800, 1600, 3200):
         s = synthetic.chain(natom, seed=3000 + natom)

@@ -164,7 +164,7 @@ using Ranges = std::vector<std::pair<int, int>>;
 // Capacities of one system from the tree, the entry capacities and the K row
 // ranges the traversal will be run over: a range's ADs have their A node
 // among the level's nodes that meet it, and its units their a shell in it.
-Caps make_caps(const fx_tree* T, long e_in, long e_leaf, const Ranges& ranges) {
+Caps make_caps(const fx_tree* T, long e_in, long e_leaf, const Ranges& ranges, const long* units_seen = nullptr) {
     Caps c;
     const int nl = (int)T->levels.size();
     c.e_in = std::max(1L, std::min(e_in, kEntryMax));
@@ -198,8 +198,12 @@ Caps make_caps(const fx_tree* T, long e_in, long e_leaf, const Ranges& ranges) {
     c.units = 0;
     for (int la = 0; la < 3; ++la)
         for (int ld = 0; ld < 3; ++ld) {
-            c.ucap[la * 3 + ld] = nra[la] * pre[ld][T->S];
-            c.units += c.ucap[la * 3 + ld];
+            long u = nra[la] * pre[ld][T->S];
+            // the counts earlier calls saw per range, with a margin: launch grids
+            // follow the units that exist rather than every (a, d) pair
+            if (units_seen) u = std::min(u, units_seen[la * 3 + ld] + units_seen[la * 3 + ld] / 4 + 1024);
+            c.ucap[la * 3 + ld] = u;
+            c.units += u;
         }
     return c;
 }
@@ -408,7 +412,10 @@ void make_units(Sys& s, hipStream_t st, const Shared& sh) {
     const long* item_off = b.off[lv & 1];
     fx_launch_unit_count(items, s.cnt, lv, c.items, T->basis.leaf_lofs, T->basis.leaf_lsh, b.ucnt, st);
     fx_scan_i32(b.ucnt, 9 * c.items, b.upos, sh.partial, sh.total, st);
-    fx_launch_unit_bounds(b.upos, c.items, s.cnt, st);
+    FxUnitCaps uc{};
+    for (int k = 0; k < 9; ++k) uc.cap[k] = c.ucap[k];
+    uc.total = c.units;
+    fx_launch_unit_bounds(b.upos, c.items, s.cnt, sh.run, uc, st);
     fx_launch_units_done(s.cnt, sh.run, st);
     fx_launch_unit_write(items, s.cnt, lv, c.items, T->basis.leaf_lofs, T->basis.leaf_lsh, b.upos, b.units, st);
     if (T->single_shell_leaves)
@@ -707,6 +714,11 @@ void absorb_usage(const fx_tree* T) {
     FxSizeHint& h = T->hint;
     // sizes per row range of that call, scaled to the whole traversal
     const long nc = std::max(1, T->usage_nchunks);
+    if (T->usage_nchunks != h.units_chunks) {
+        h.units_chunks = T->usage_nchunks;
+        for (int k = 0; k < 9; ++k) h.units_max[k] = 0;
+    }
+    for (int k = 0; k < 9; ++k) h.units_max[k] = std::max(h.units_max[k], u.ucls[k]);
     if (T->usage_nchunks == h.range_chunks) {
         h.range_e_in = std::max({h.range_e_in, u.e_in, u.need_in});
         h.range_e_leaf = std::max({h.range_e_leaf, u.e_leaf, u.need_leaf, u.need_in});
@@ -861,7 +873,11 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
             ei = (long)(m * (double)h.e_in / nch) + 1024;
             el = (long)(m * (double)h.e_leaf / nch) + 1024;
         }
-        s.caps = make_caps(s.T, ei, el, nch > 1 ? row_ranges(s.T, nch) : whole_rows(s.T));
+        // (calls that wait keep the bounds from the tree: they split a row range
+        // that overflows, which the unit lists could not undo)
+        const bool seen = o.max_frontier_entries == 0 && !cs.op.wait && h.units_chunks == nch &&
+                          *std::max_element(h.units_max, h.units_max + 9) > 0;
+        s.caps = make_caps(s.T, ei, el, nch > 1 ? row_ranges(s.T, nch) : whole_rows(s.T), seen ? h.units_max : nullptr);
     };
     int nchunks = 1;
     if (noalloc && o.max_frontier_entries == 0) {
@@ -1167,11 +1183,13 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
                 }
             }
         }
-        // K = alpha * acc + beta * K (NaN where a chunk overflowed)
+        // a call that waits has run every overflowed row range again
+        if (check) fx_launch_fill_i32(&sh.run->incomplete, 1, 0, ls);
+        // K = alpha * acc + beta * K (NaN if a chunk overflowed and was not run again)
         for (auto& s : sys) {
             const long nn = (long)s.T->n * s.T->n;
             for (int j = 0; j < ndens; ++j)
-                fx_launch_finalize(s.b.acc[j], nn, o.alpha, o.beta, s.K[j], &s.cnt->overflow, ls);
+                fx_launch_finalize(s.b.acc[j], nn, o.alpha, o.beta, s.K[j], &sh.run->incomplete, ls);
         }
         FX_HIP(hipGetLastError());
     };
@@ -1202,7 +1220,8 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
         bool hit = gc && gc->key == key && gc->caps.size() == sys.size();
         if (hit)
             for (int i = 0; i < count; ++i)
-                hit &= gc->caps[i].e_in >= sys[i].caps.e_in && gc->caps[i].e_leaf >= sys[i].caps.e_leaf;
+                hit &= gc->caps[i].e_in >= sys[i].caps.e_in && gc->caps[i].e_leaf >= sys[i].caps.e_leaf &&
+                       std::equal(gc->caps[i].ucap, gc->caps[i].ucap + 9, sys[i].caps.ucap);
         if (hit) {
             for (int i = 0; i < count; ++i) sys[i].caps = gc->caps[i];
         } else {

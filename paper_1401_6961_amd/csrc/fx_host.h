@@ -162,6 +162,9 @@ struct FxSizeHint {
     int range_chunks = 0;
     long range_e_in = 0, range_e_leaf = 0;
     std::vector<long> leaf_rows;   // leaf entries per leaf row of the whole traversal (empty: unknown)
+    // largest unit count per (la, ld) of one row range, at units_chunks ranges (0: not seen)
+    int units_chunks = 0;
+    long units_max[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     // the row-range count last chosen, and what it was chosen for
     int plan_chunks = 0, plan_range_chunks = 0;
     size_t plan_budget = 0;

@@ -69,10 +69,17 @@ struct FxDevCounts {
 struct FxDevRun {
     long e_in, e_leaf;                // largest inner / leaf entry counts of a chunk (next call's capacities)
     long need_in, need_leaf;          // largest requests of an inner / the leaf level that exceeded its capacity
-    int overflow;                     // some chunk exceeded a capacity (its K is NaN)
-    int pad;
+    int overflow;                     // some chunk exceeded a capacity
+    int incomplete;                   // some chunk that exceeded a capacity was not run again: K is NaN
     long frontier[FX_MAX_LEVELS];     // entries per level, summed over the completed chunks
     long items, units;                // leaf (A, D) items and K-block units, summed
+    long ucls[9];                     // largest unit count per (la, ld) of a chunk (next call's capacities)
+};
+
+// Unit capacities of one chunk per (la, ld), and of its whole unit list.
+struct FxUnitCaps {
+    long cap[9];
+    long total;
 };
 
 // One system (or traversal chunk) as seen by the class kernels.

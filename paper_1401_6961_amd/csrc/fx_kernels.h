@@ -75,7 +75,8 @@ void fx_launch_screen_group(const int2* items, const long* item_off, const int2*
                             double tau_ovlp, uint32_t* mask, hipStream_t st);
 void fx_launch_leaf_rows(const int2* items, const long* off, const FxDevCounts* cnt, int lv, long cap,
                          unsigned long long* rows, hipStream_t st);
-void fx_launch_unit_bounds(const long* upos, long cap, FxDevCounts* cnt, hipStream_t st);
+void fx_launch_unit_bounds(const long* upos, long cap, FxDevCounts* cnt, FxDevRun* run, const FxUnitCaps& uc,
+                           hipStream_t st);
 void fx_launch_unit_write(const int2* items, const FxDevCounts* cnt, int lv, long cap, const int* leaf_lofs,
                           const int* leaf_lsh, const long* upos, int* units, hipStream_t st);
 void fx_launch_merge_bounds(const FxDevCounts* cnts, int nsys, int k2, long* moff, long* mb, hipStream_t st);

@@ -517,6 +517,7 @@ __global__ void fx_k_chunk_done(const FxDevCounts* cnt, int nl, const unsigned l
         if (cnt->ne[nl - 1] > run->e_leaf) run->e_leaf = cnt->ne[nl - 1];
         if (!ok) {
             run->overflow = 1;
+            run->incomplete = 1;
             long* w = cnt->need_level == nl - 1 ? &run->need_leaf : &run->need_in;
             if (cnt->need > *w) *w = cnt->need;
         } else {
@@ -794,20 +795,39 @@ void fx_launch_leaf_rows(const int2* items, const long* off, const FxDevCounts* 
 }
 
 // unit list bounds per (la, ld) from the scanned counts
-__global__ void fx_k_unit_bounds(const long* __restrict__ upos, long cap, FxDevCounts* cnt) {
-    const int k = threadIdx.x;
-    if (k < 10) cnt->ubase[k] = upos[(long)k * cap];
+// Unit list bounds per (la, ld) from the scanned counts.  Counts above the
+// chunk's unit capacities (taken from earlier calls) mark the chunk as
+// overflowed and leave every list empty, so no kernel writes past the unit
+// buffer; the counts are recorded for the next call's capacities.
+__global__ void fx_k_unit_bounds(const long* __restrict__ upos, long cap, FxDevCounts* cnt, FxDevRun* run,
+                                 FxUnitCaps uc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    long b[10];
+    for (int k = 0; k < 10; ++k) b[k] = upos[(long)k * cap];
+    bool over = b[9] > uc.total;
+    for (int k = 0; k < 9; ++k) {
+        const long n = b[k + 1] - b[k];
+        if (n > uc.cap[k]) over = true;
+        if (n > run->ucls[k]) run->ucls[k] = n;
+    }
+    if (over && !cnt->overflow) {
+        cnt->overflow = 1;
+        run->overflow = 1;
+        run->incomplete = 1;
+    }
+    for (int k = 0; k < 10; ++k) cnt->ubase[k] = cnt->overflow ? 0 : b[k];
 }
 
-void fx_launch_unit_bounds(const long* upos, long cap, FxDevCounts* cnt, hipStream_t st) {
-    hipLaunchKernelGGL(fx_k_unit_bounds, dim3(1), dim3(64), 0, st, upos, cap, cnt);
+void fx_launch_unit_bounds(const long* upos, long cap, FxDevCounts* cnt, FxDevRun* run, const FxUnitCaps& uc,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(fx_k_unit_bounds, dim3(1), dim3(64), 0, st, upos, cap, cnt, run, uc);
 }
 
 __global__ __launch_bounds__(256) void fx_k_unit_write(const int2* __restrict__ items, const FxDevCounts* cnt, int lv,
                                                        long cap, const int* __restrict__ leaf_lofs,
                                                        const int* __restrict__ leaf_lsh, const long* __restrict__ upos,
                                                        int* __restrict__ units) {
-    const long nitems = cnt->nad[lv];
+    const long nitems = cnt->overflow ? 0 : cnt->nad[lv];
     const int sym = cnt->sym;
     for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < 9 * cap; t += (long)gridDim.x * blockDim.x) {
         const int cls = (int)(t / cap);
