@@ -251,7 +251,7 @@ void carve_sys(Carve& cv, Sys& s, int ndens, bool own_acc) {
         b.cls_off = cv.take<long>(10 * c.items);
     }
     b.cpart = cv.take<unsigned long long>(3 * FX_PART_SLOTS);
-    if (group_screen(T)) b.screen = cv.take<uint32_t>(c.e_leaf);
+    if (g_group_screen && group_screen(T)) b.screen = cv.take<uint32_t>(c.e_leaf);
     for (int j = 0; j < ndens; ++j) b.acc[j] = own_acc ? cv.take<double>((size_t)T->n * T->n) : nullptr;
 }
 
@@ -1038,7 +1038,8 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
                 return hi;
             };
             const bool planned = h.plan_chunks > 0 && h.plan_budget == budget && h.plan_e_in == h.e_in &&
-                                 h.plan_e_leaf == h.e_leaf && h.plan_range_chunks == h.range_chunks;
+                                 h.plan_e_leaf == h.e_leaf && h.plan_range_chunks == h.range_chunks &&
+                                 h.plan_screen == g_group_screen;
             if (planned) {
                 nchunks = h.plan_chunks;
             } else if (layout(nullptr) > budget) {
@@ -1098,6 +1099,7 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
                 h.plan_e_in = h.e_in;
                 h.plan_e_leaf = h.e_leaf;
                 h.plan_range_chunks = h.range_chunks;
+                h.plan_screen = g_group_screen;
             }
             caps_from_hint(sys[0], nchunks);
         }

@@ -166,7 +166,7 @@ struct FxSizeHint {
     int units_chunks = 0;
     long units_max[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     // the row-range count last chosen, and what it was chosen for
-    int plan_chunks = 0, plan_range_chunks = 0;
+    int plan_chunks = 0, plan_range_chunks = 0, plan_screen = 0;
     size_t plan_budget = 0;
     long plan_e_in = 0, plan_e_leaf = 0;
 };
