@@ -335,6 +335,11 @@ def main():
                  "mixed_speedup_vs_fp64": t64 / (elapsed / args.steps),
                  "mixed_err_maxabs": float(dK.max()), "mixed_err_frob": float(torch.linalg.norm(K - K64)),
                  "mixed_err_exchange_energy": float(abs(0.25 * ((P * (K - K64)).sum()))),
+                 # a-priori bound of the Frobenius change: c * u32 * sum of beta over the FP32
+                 # quartets (u32 = 2^-24), given here for c = 1 (c is the growth of a quartet's
+                 # FP32 rounding through its recurrences)
+                 "mixed_err_bound_frob_c1": 2.0 ** -24 * st["fp32_beta_sum"],
+                 "fp32_beta_sum": st["fp32_beta_sum"],
                  "mixed_err_note": "mixed K minus FP64 K of this library (the FP64 path matches the oracle to "
                                    "1e-10 in the tests); FP32 instructions issue at the FP64 rate here (packed "
                                    "FP32 is off), so the speed-up comes from smaller register and private-memory "

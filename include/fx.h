@@ -183,6 +183,10 @@ typedef struct fx_stats {
     int32_t overflow;                            /* 1: a traversal level exceeded its capacity and the call
                                                     split its K rows and ran them again (K is complete) */
     int64_t workspace_bytes;                     /* device workspace of the call */
+    double fp32_beta_sum;                        /* mixed precision: sum of the bounds beta_q (Eq. 8) of the
+                                                    quartets evaluated in FP32; with the FP32 unit roundoff
+                                                    u = 2^-24 and a per-quartet growth factor c, c*u times
+                                                    this bounds the Frobenius change of K a priori */
 } fx_stats;
 
 /* Build the basis-function tree for a set of shells: normalisation, shell

@@ -160,7 +160,8 @@ constexpr int fx_qcap() { return 64 * (G + 1); }
 
 template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, int NDENS, bool DUAL, int G, typename Fn, typename Fn2>
 __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 fn2, long slot_unit, int wave,
-                                              int2 (*queue)[fx_qcap<G>()], int2 (*queue2)[fx_qcap<G>()]) {
+                                              int2 (*queue)[fx_qcap<G>()], int2 (*queue2)[fx_qcap<G>()],
+                                              double* b32s) {
     static_assert(!COOP || NDENS == 1, "the one-quartet-per-wave form contracts one density");
     static_assert(!COOP || !DUAL, "the one-quartet-per-wave form runs one precision");
     constexpr int NA = fx_ncart(LA), ND = fx_ncart(LD);
@@ -203,6 +204,9 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
         f(ra, rb, rc, rd, Bs, A.boys, Pq, Sy.n, kacc, wave);
     };
     // 0: culled; 1: first queue; 2: second queue (DUAL, beta < thr)
+    // statistics calls: sum of beta over the FP32 quartets (a-priori error bound),
+    // gathered in the wave's LDS slot so that it holds no register
+    if (A.beta32 && lane == 0) b32s[wave] = 0.0;
     auto test = [&](int b, int c) -> int {
         const double beta = (Qa[b] * Qd[c]) * Sy.Pn[(long)b * S + c];
         // leaf_screen BLOCK: every quartet of a surviving leaf task is computed
@@ -210,9 +214,14 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
         // overlap criterion of Eqs. (3)-(4): a pair of shells whose functions
         // all overlap less than tau_ovlp contributes nothing
         if (ovlp && !(Sa[b] >= tau_ovlp && Sd[c] >= tau_ovlp)) return 0;
-        if (DUAL) return beta < thr ? 2 : 1;
+        if (DUAL || mode == FX_MODE_MIXED_LO) {
+            if (beta < thr) {
+                if (A.beta32) atomicAdd(&b32s[wave], beta);
+                return DUAL ? 2 : 1;
+            }
+            return DUAL ? 1 : 0;
+        }
         if (mode == FX_MODE_MIXED_HI) return beta < thr ? 0 : 1;
-        if (mode == FX_MODE_MIXED_LO) return beta < thr ? 1 : 0;
         return 1;
     };
     // a stored screen outcome (0 culled, 1 beta >= thr, 2 beta < thr) as `test` returns it
@@ -402,6 +411,10 @@ __device__ __forceinline__ void fx_class_unit(const FxClassArgs& A, Fn fn, Fn2 f
     };
     if (A.counters) count(A.counters, nq, npq);
     if (DUAL && A.counters2) count(A.counters2, nq2, npq2);
+    if (A.beta32 && (DUAL || mode == FX_MODE_MIXED_LO)) {
+        fx_wave_sync();
+        if (lane == 0 && b32s[wave] != 0.0) atomicAdd(A.beta32, b32s[wave]);
+    }
 }
 
 // Kernel-level unit loop: one unit per wave, with an optional XCD-aware remap
@@ -413,12 +426,13 @@ template <int LA, int LB, int LC, int LD, bool COOP, int WAVES, int NDENS, bool 
 __device__ __forceinline__ void fx_class_body(const FxClassArgs& A, Fn fn, Fn2 fn2) {
     __shared__ int2 queue[WAVES][fx_qcap<G>()];
     __shared__ int2 queue2[DUAL ? WAVES : 1][fx_qcap<G>()];
+    __shared__ double b32s[WAVES];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     long blk = blockIdx.x;
     if (A.flags & FX_LAUNCH_XCD) blk = fx_xcd_remap(blk, gridDim.x);
     const long slot_unit = blk * WAVES + wave;
     if (slot_unit >= __builtin_amdgcn_readfirstlane((int)(A.ulh[1] - A.ulh[0]))) return;
-    fx_class_unit<LA, LB, LC, LD, COOP, WAVES, NDENS, DUAL, G>(A, fn, fn2, slot_unit, wave, queue, queue2);
+    fx_class_unit<LA, LB, LC, LD, COOP, WAVES, NDENS, DUAL, G>(A, fn, fn2, slot_unit, wave, queue, queue2, b32s);
 }
 
 // Thread variant: one quartet per lane.

@@ -128,6 +128,7 @@ struct Shared {
     FxDevCounts* cnts = nullptr;              // one per system
     FxDevRun* run = nullptr;                  // call totals and sizes seen (next call's capacities)
     unsigned long long* rows = nullptr;       // leaf entries per leaf row (first call on a tree)
+    double* beta32 = nullptr;                 // sum of beta over the quartets evaluated in FP32
     long* partial = nullptr;
     long* total = nullptr;
     // scheduling
@@ -259,6 +260,7 @@ void carve_shared(Carve& cv, Shared& sh, std::vector<Sys>& sys, const Opts& op) 
     const int count = (int)sys.size();
     sh.counters = cv.take<unsigned long long>(81 * 2 * 3 + 3 * FX_PART_SLOTS);
     sh.part = sh.counters ? sh.counters + 81 * 2 * 3 : nullptr;
+    sh.beta32 = cv.take<double>(1);
     sh.cnts = cv.take<FxDevCounts>(count);
     sh.run = cv.take<FxDevRun>(1);
     size_t nleaf = 1;
@@ -459,6 +461,8 @@ void run_classes(CallState& cs, std::vector<Sys*>& sys, std::vector<FxSys>& ysys
     args.thr = op.o.fp32_threshold;
     args.tau_ovlp = op.o.tau_ovlp;
     args.block = op.o.leaf_screen == FX_LEAF_BLOCK ? 1 : 0;
+    // statistics calls only, and not those that time every launch
+    args.beta32 = cs.stats && !op.o.profile ? sh.beta32 : nullptr;
     const float* mean_np = sys[0]->T->mean_np;
     std::vector<float> hfeat, htime;
     for (int la = 0; la <= lmax; ++la)
@@ -1111,6 +1115,7 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
     int runs = 0;
     auto enqueue_all = [&](hipStream_t ls, bool check, bool report) {
         fx_launch_fill_u64(sh.counters, 81 * 2 * 3 + 3 * FX_PART_SLOTS, 0ull, ls);
+        fx_launch_fill_u64((unsigned long long*)sh.beta32, 1, 0ull, ls);
         fx_launch_fill_u64((unsigned long long*)sh.run, sizeof(FxDevRun) / 8, 0ull, ls);
         for (auto& s : sys) {
             for (int j = 0; j < ndens; ++j) {
@@ -1303,8 +1308,11 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
     FX_HIP(hipMemcpyAsync(hc.data(), sh.cnts, sizeof(FxDevCounts) * count, hipMemcpyDeviceToHost, st));
     FxDevRun run;
     FX_HIP(hipMemcpyAsync(&run, sh.run, sizeof(run), hipMemcpyDeviceToHost, st));
+    double beta32 = 0.0;
+    FX_HIP(hipMemcpyAsync(&beta32, sh.beta32, sizeof(double), hipMemcpyDeviceToHost, st));
     FX_HIP(hipStreamSynchronize(st));
     if (!stats) return;
+    stats->fp32_beta_sum = beta32;
     for (int k = 0; k < FX_STATS_MAX_LEVELS && k < FX_MAX_LEVELS; ++k) stats->frontier[k] = run.frontier[k];
     stats->leaf_items = run.items;
     stats->units = run.units;

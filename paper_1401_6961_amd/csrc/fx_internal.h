@@ -131,6 +131,7 @@ struct FxClassArgs {
                                       // for their mirror (symmetric system, a != d) (nullable)
     unsigned long long* counters2;    // DUAL: the same for the FP32 quartets (nullable)
     float* times;                     // per-unit wall-clock ticks (nullable; timing probes)
+    double* beta32;                   // sum of the bounds beta of the quartets evaluated in FP32 (nullable)
 };
 
 // launches one wave per unit; returns the variant launched (0 one quartet

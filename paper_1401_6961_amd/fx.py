@@ -62,7 +62,8 @@ class fx_stats(ctypes.Structure):
                 ("seconds_traversal", ctypes.c_double), ("seconds_eri", ctypes.c_double),
                 ("seconds_total", ctypes.c_double), ("quartets_covered", ctypes.c_int64),
                 ("symmetric_systems", ctypes.c_int32), ("partition", ctypes.c_int64 * 3),
-                ("overflow", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64)]
+                ("overflow", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
+                ("fp32_beta_sum", ctypes.c_double)]
 
     def as_dict(self):
         return {"levels": self.levels, "frontier": list(self.frontier)[: self.levels],
@@ -76,6 +77,7 @@ class fx_stats(ctypes.Structure):
                 "symmetric_systems": self.symmetric_systems,
                 "partition": [int(x) for x in self.partition],
                 "overflow": int(self.overflow), "workspace_bytes": int(self.workspace_bytes),
+                "fp32_beta_sum": float(self.fp32_beta_sum),
                 "class_seconds": np.array(self.class_seconds).reshape(81, 2),
                 "class_launches": np.array(self.class_launches).reshape(81, 2),
                 "class_flops": np.array(self.class_flops).reshape(81, 2),

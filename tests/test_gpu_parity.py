@@ -243,6 +243,38 @@ def test_cooperative_variants(spd5):
             fx.fx_set_class_variant(cls, p, v)
 
 
+def test_fp32_bound_sum(spd5):
+    """Mixed precision, every K block built (no symmetry): the statistic
+    fp32_beta_sum equals the sum of beta_q = (Q_ab Q_cd) ||P_bc|| (Eq. 8)
+    over the quartets with tau < beta_q < fp32_threshold, in one pass and in
+    two passes per class; 0 in FP64."""
+    say("gpu: sum of beta over the FP32 quartets")
+    tau, thr = 1e-11, 1e-5
+    tree = fx.build_quadtree_from(spd5)
+    Q = tree.schwarz()
+    Pn = oracle.pnorm(spd5, spd5.P)
+    beta = (Q[:, :, None, None] * Q[None, None, :, :]) * Pn[None, :, :, None]   # beta[a,b,c,d]
+    sel = (beta > tau) & (beta < thr)
+    ref = float(beta[sel].sum())
+    # quartets within rounding of a threshold could go either way on the device
+    near = (np.abs(beta / tau - 1) < 1e-12) | (np.abs(beta / thr - 1) < 1e-12)
+    slack = float(beta[near].sum()) + 1e-12 * ref
+    saved = {c: fx.fx_get_class_variant(c, 0) for c in range(81)}
+    try:
+        for v in (2, 0):
+            for c in range(81):
+                fx.fx_set_class_variant(c, 0, v)
+            _, st, _ = gpu_exchange(spd5, tau, tree=tree, precision=fx.FX_PREC_MIXED, fp32_threshold=thr,
+                                    symmetry=fx.FX_SYM_OFF)
+            assert st["quartets_fp32"] > 0
+            assert abs(st["fp32_beta_sum"] - ref) <= slack, (v, st["fp32_beta_sum"], ref)
+    finally:
+        for c, v in saved.items():
+            fx.fx_set_class_variant(c, 0, v)
+    _, st64, _ = gpu_exchange(spd5, tau, tree=tree, symmetry=fx.FX_SYM_OFF)
+    assert st64["fp32_beta_sum"] == 0.0
+
+
 def test_one_pass_mixed_matches_two_passes(spd5):
     """Mixed precision with both precisions in one kernel (variant 2) and in
     two kernels per class: the same quartets in each precision, K equal to
