@@ -205,8 +205,9 @@ fx_status fx_build_quadtree(const fx_shells* shells, const fx_tree_opts* opts, v
  * Asynchronous: the work is enqueued on `stream` and the call returns
  * without waiting for it; P must stay unchanged and K unread until the
  * stream reaches that point.  Every size the traversal produces stays on the
- * device.  Buffers are sized from the sizes earlier calls on the same tree
- * needed (with a 25% margin); the first call on a tree learns them in a
+ * device.  Buffers (traversal levels, K-block unit lists) and launch grids
+ * are sized from the sizes earlier calls on the same tree needed (with a
+ * 25% margin); the first call on a tree learns the traversal sizes in a
  * traversal-only pass, for which it waits.  If a later call needs more than
  * its buffers hold, that call writes NaN into K (and, when it waits for
  * statistics, redoes the work in K row ranges and returns the right K); the
