@@ -352,6 +352,17 @@ int64_t fx_xcd_block(int64_t b, int64_t nb);
 /* Bit mask of the variants built for a class (bit v = variant v). */
 int32_t fx_class_variants_available(int32_t cls);
 
+/* Host-only planning helper (no device work): the cuts that split a row of
+ * nleaf leaf blocks into nchunks contiguous, non-empty K row ranges, as a
+ * call whose workspace budget needs several ranges takes them.
+ * leaf_entries[nleaf] (host, nullable): traversal entries per leaf row; the
+ * ranges then hold about equal entries (cut k at the first leaf boundary
+ * where the running sum reaches k/nchunks of the total), else about equal
+ * leaf counts.  cuts[nchunks + 1] (host, caller-owned): range k is leaves
+ * [cuts[k], cuts[k+1]); nchunks above nleaf is reduced to nleaf and the
+ * cuts beyond it are nleaf. */
+fx_status fx_plan_row_cuts(const int64_t* leaf_entries, int32_t nleaf, int32_t nchunks, int32_t* cuts);
+
 /* Shared screen per (l_a, l_d) group (default off): where every leaf holds at
  * most one shell of each angular momentum, one kernel per group tests each
  * entry's nine (l_b, l_c) candidates with the bound of Eq. (8) and the

@@ -8,4 +8,4 @@ from .fx import (FX_PREC_FP64, FX_PREC_MIXED, FX_SCHED_BOUND, FX_SCHED_MLP, FX_S
                  fx_plan_tree, lib, make_opts, fx_set_class_variant, fx_get_class_variant,
                  fx_class_variants_available, CostModel, TaskTimings, fx_record_task_timings,
                  fx_costmodel_train, fx_set_class_launch, fx_get_class_launch, set_progress_stderr,
-                 set_group_screen, get_group_screen)
+                 set_group_screen, get_group_screen, plan_row_cuts)

@@ -675,21 +675,19 @@ int split_rows(const fx_tree* T, int lo, int hi) {
     return best;
 }
 
-// nchunks K row ranges at leaf boundaries: of about equal leaf entries when
-// the tree has counted them, else of about equal leaf counts
-Ranges row_ranges(const fx_tree* T, int nchunks) {
-    const Level& leaf = T->levels.back();
-    const int nleaf = (int)leaf.sL.size();
+// Cuts of nleaf leaves into nchunks contiguous, non-empty ranges [cut[k],
+// cut[k+1]): of about equal entries when `rows` (entries per leaf) is given
+// and not all zero, else of about equal leaf counts.  Cut k is the first
+// leaf boundary where the running sum reaches k/nchunks of the total, moved
+// only as far as keeping every range non-empty needs.
+std::vector<int> leaf_cuts(const long* rows, int nleaf, int nchunks) {
     nchunks = std::max(1, std::min(nchunks, nleaf));
     std::vector<int> cut(nchunks + 1, nleaf);
     cut[0] = 0;
-    const std::vector<long>& rows = T->hint.leaf_rows;
     long total = 0;
-    if ((int)rows.size() == nleaf)
-        for (long x : rows) total += x;
+    if (rows)
+        for (int i = 0; i < nleaf; ++i) total += rows[i];
     if (total > 0) {
-        // cut c at the first leaf whose running sum reaches c/nchunks of the total,
-        // keeping at least one leaf per range
         long run = 0;
         int c = 1;
         for (int i = 0; i < nleaf && c < nchunks; ++i) {
@@ -701,8 +699,19 @@ Ranges row_ranges(const fx_tree* T, int nchunks) {
     } else {
         for (int k = 1; k < nchunks; ++k) cut[k] = (int)((long)k * nleaf / nchunks);
     }
+    return cut;
+}
+
+// nchunks K row ranges at leaf boundaries: of about equal leaf entries when
+// the tree has counted them, else of about equal leaf counts
+Ranges row_ranges(const fx_tree* T, int nchunks) {
+    const Level& leaf = T->levels.back();
+    const int nleaf = (int)leaf.sL.size();
+    const std::vector<long>& rows = T->hint.leaf_rows;
+    const std::vector<int> cut = leaf_cuts((int)rows.size() == nleaf ? rows.data() : nullptr, nleaf, nchunks);
     Ranges r;
-    for (int k = 0; k < nchunks; ++k) r.push_back({leaf.sL[cut[k]], cut[k + 1] < nleaf ? leaf.sL[cut[k + 1]] : T->S});
+    for (size_t k = 0; k + 1 < cut.size(); ++k)
+        r.push_back({leaf.sL[cut[k]], cut[k + 1] < nleaf ? leaf.sL[cut[k + 1]] : T->S});
     return r;
 }
 
@@ -1354,6 +1363,20 @@ void fx_exchange_run(const fx_tree* const* trees, const double* const* Ps, doubl
 // C ABI: exchange entry points
 // ---------------------------------------------------------------------------
 extern "C" {
+
+fx_status fx_plan_row_cuts(const int64_t* leaf_entries, int32_t nleaf, int32_t nchunks, int32_t* cuts) {
+    return fx_guard([&] {
+        if (nleaf < 1 || nchunks < 1 || !cuts) fx_fail(FX_ERR_INVALID_ARG, "need nleaf >= 1, nchunks >= 1, cuts");
+        std::vector<long> rows;
+        if (leaf_entries) {
+            rows.assign(leaf_entries, leaf_entries + nleaf);
+            for (long x : rows)
+                if (x < 0) fx_fail(FX_ERR_INVALID_ARG, "negative entry count");
+        }
+        const std::vector<int> cut = leaf_cuts(leaf_entries ? rows.data() : nullptr, nleaf, nchunks);
+        for (int k = 0; k <= nchunks; ++k) cuts[k] = k < (int)cut.size() ? cut[k] : nleaf;
+    });
+}
 
 fx_status fx_set_group_screen(int32_t enabled) {
     return fx_guard([&] { g_group_screen = enabled ? 1 : 0; });

@@ -95,7 +95,7 @@ EXPORTED = ["fx_build_quadtree", "fx_exchange", "fx_exchange_ex", "fx_exchange_o
             "fx_task_timings_free", "fx_costmodel_train", "fx_costmodel_nparams", "fx_costmodel_create",
             "fx_costmodel_params", "fx_costmodel_predict", "fx_costmodel_loss_grad", "fx_costmodel_free",
             "fx_costmodel_save", "fx_costmodel_load", "fx_set_progress", "fx_progress_stderr",
-            "fx_set_group_screen", "fx_get_group_screen"]
+            "fx_set_group_screen", "fx_get_group_screen", "fx_plan_row_cuts"]
 
 
 def lib():
@@ -123,6 +123,8 @@ def lib():
     L.fx_exchange_opts_init.restype = None
     L.fx_set_progress.argtypes = [vp, vp]
     L.fx_set_progress.restype = ctypes.c_int
+    L.fx_plan_row_cuts.argtypes = [vp, i32, i32, ctypes.POINTER(i32)]
+    L.fx_plan_row_cuts.restype = ctypes.c_int
     L.fx_set_group_screen.argtypes = [i32]
     L.fx_set_group_screen.restype = ctypes.c_int
     L.fx_get_group_screen.argtypes = []
@@ -291,6 +293,23 @@ def fx_build_quadtree(l, nprim, center, exps, coefs, leaf_max_functions=0, order
 def build_quadtree_from(system, **kw) -> Tree:
     """Convenience: a synthetic.System-like object with l, nprim, center, exps, coefs."""
     return fx_build_quadtree(system.l, system.nprim, system.center, system.exps, system.coefs, **kw)
+
+
+def plan_row_cuts(leaf_entries, nchunks: int, nleaf: int | None = None) -> np.ndarray:
+    """Host-only: the leaf cuts of nchunks K row ranges (fx_plan_row_cuts);
+    leaf_entries None gives ranges of about equal leaf counts."""
+    if leaf_entries is None:
+        if nleaf is None:
+            raise ValueError("give leaf_entries or nleaf")
+        ptr = None
+    else:
+        le = np.ascontiguousarray(leaf_entries, dtype=np.int64)
+        nleaf = le.shape[0]
+        ptr = le.ctypes.data
+    cuts = np.zeros(int(nchunks) + 1, dtype=np.int32)
+    _check(lib().fx_plan_row_cuts(ptr, int(nleaf), int(nchunks),
+                                  cuts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return cuts
 
 
 def set_group_screen(enabled: bool) -> None:

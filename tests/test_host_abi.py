@@ -187,3 +187,35 @@ def test_costmodel_load_rejects_foreign_files(tmp_path):
     bad.write_bytes(b"FXMLP001" + b"\x00" * 12)
     assert L.fx_costmodel_load(os.fsencode(str(bad)), C.byref(h)) == 1
     assert not h.value
+
+
+def test_row_cuts_partition_the_leaves_and_balance_the_entries():
+    """K row ranges for the workspace budget: contiguous, non-empty, covering
+    every leaf; each range's entries exceed an equal share by less than its
+    largest leaf; with no counts, leaf counts differ by at most one."""
+    rng = np.random.default_rng(11)
+    for trial in range(50):
+        nleaf = int(rng.integers(1, 400))
+        rows = rng.integers(0, 1000, nleaf) * (rng.random(nleaf) < 0.9)
+        if trial % 5 == 0:
+            rows[: nleaf // 2] *= 50          # a heavy block of rows
+        n = int(rng.integers(1, nleaf + 3))
+        cuts = fx.plan_row_cuts(rows, n)
+        m = min(n, nleaf)
+        assert cuts[0] == 0 and cuts[m] == nleaf and np.all(cuts[m:] == nleaf)
+        assert np.all(np.diff(cuts[: m + 1]) >= 1)
+        total = int(rows.sum())
+        if total > 0 and m > 1:
+            for k in range(m):
+                seg = rows[cuts[k]:cuts[k + 1]]
+                assert seg.sum() <= total / m + rows.max() * 2, (trial, k)
+        even = fx.plan_row_cuts(None, n, nleaf=nleaf)
+        sizes = np.diff(even[: m + 1])
+        assert sizes.min() >= 1 and sizes.max() - sizes.min() <= 1
+
+
+def test_row_cuts_reject_bad_arguments():
+    with pytest.raises(fx.FxError):
+        fx.plan_row_cuts(np.array([1, -2, 3]), 2)
+    with pytest.raises(fx.FxError):
+        fx.plan_row_cuts(None, 0, nleaf=5)
