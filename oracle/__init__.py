@@ -39,11 +39,12 @@ def lib():
         L.fxo_exchange_leafblock.argtypes = shells + [f64p, ctypes.c_double, ctypes.c_int, f64p, f64p]
         L.fxo_overlap.argtypes = shells + [f64p, ctypes.c_void_p]
         L.fxo_exchange_ovlp.argtypes = shells + [f64p, ctypes.c_double, ctypes.c_double, f64p, f64p]
+        L.fxo_exchange_sym8.argtypes = shells + [f64p, ctypes.c_double, f64p, f64p]
         L.fxo_count.argtypes = [ctypes.c_int, i32p, i32p, f64p, f64p, ctypes.c_double, f64p,
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         for f in ("fxo_norm_coefs", "fxo_eri_quartet", "fxo_eri_tensor", "fxo_schwarz", "fxo_pnorm",
                   "fxo_exchange", "fxo_exchange_blocks", "fxo_bound_matrix", "fxo_count", "fxo_exchange_leafblock",
-                  "fxo_overlap", "fxo_exchange_ovlp"):
+                  "fxo_overlap", "fxo_exchange_ovlp", "fxo_exchange_sym8"):
             getattr(L, f).restype = ctypes.c_int
         L.fxo_num_threads.restype = ctypes.c_int
         L.fxo_set_threads.argtypes = [ctypes.c_int]
@@ -156,6 +157,21 @@ def exchange_ovlp(s, tau_ovlp, P=None, tau=None):
     _check(lib().fxo_exchange_ovlp(*_sh(s), np.ascontiguousarray(P, np.float64), float(tau), float(tau_ovlp), K,
                                    st), "exchange_ovlp")
     return K.reshape(n, n), {"quartets": int(st[0]), "near_threshold": int(st[1]), "beta_quartets": int(st[3])}
+
+
+def exchange_sym8(s, P=None, tau=None):
+    """K through the permutational symmetry of Section IV: each unique shell
+    quartet evaluated once and contracted into every ordered quartet it
+    stands for that its own bound keeps.  stats: unique quartets evaluated,
+    ordered quartets contracted, primitive quartets evaluated."""
+    P = s.P if P is None else P
+    tau = s.tau if tau is None else tau
+    n = s.nbf
+    K = np.zeros(n * n)
+    st = np.zeros(3)
+    _check(lib().fxo_exchange_sym8(*_sh(s), np.ascontiguousarray(P, np.float64), float(tau), K, st),
+           "exchange_sym8")
+    return K.reshape(n, n), {"integrals": int(st[0]), "quartets": int(st[1]), "prim_quartets": int(st[2])}
 
 
 def exchange_blocks(s, pairs, P=None, tau=None, Qn=None, Pn=None):

@@ -527,6 +527,92 @@ int fxo_exchange(int nshell, const int32_t* l, const int32_t* nprim, const doubl
 }
 
 /*
+ * Screened exchange through the permutational symmetry of the integrals
+ * (Section IV, Eqs. 9-10).  Every unique shell quartet is taken once, in the
+ * canonical order a >= b, c >= d, ab >= cd (pair index ab = a(a+1)/2 + b),
+ * its integrals are evaluated once, and they are contracted into the K block
+ * of every distinct ordered quartet they stand for -- (ab|cd), (ba|cd),
+ * (ab|dc), (ba|dc) and the four with the two pairs exchanged, an integral
+ * (pq|rs) adding (pq|rs) P_qr to K_ps -- each kept under its own bound
+ * beta = (Qn_pq Qn_rs) Pn_qr > tau, as fxo_exchange keeps it.  The result is
+ * therefore fxo_exchange's K up to the order of the sums, while the
+ * integral evaluations drop to about an eighth.  tau < 0: every quartet.
+ * Serial: the contributions of one integral land in up to eight K blocks.
+ * stats (nullable): [0] unique quartets whose integrals were evaluated,
+ * [1] ordered quartets contracted (fxo_exchange's computed count), [2]
+ * primitive quartets of the evaluated integrals.
+ */
+int fxo_exchange_sym8(int nshell, const int32_t* l, const int32_t* nprim, const double* center,
+                      const double* exps, const double* coefs, const double* P, double tau, double* K,
+                      double* stats) {
+    static const int perm[8][4] = {{0, 1, 2, 3}, {1, 0, 2, 3}, {0, 1, 3, 2}, {1, 0, 3, 2},
+                                   {2, 3, 0, 1}, {3, 2, 0, 1}, {2, 3, 1, 0}, {3, 2, 1, 0}};
+    obasis B;
+    if (make_basis(&B, nshell, l, nprim, center, exps, coefs)) return -1;
+    int S = nshell, n = B.nbf;
+    double* Qn = (double*)malloc(sizeof(double) * (size_t)S * S);
+    double* Pn = (double*)malloc(sizeof(double) * (size_t)S * S);
+    schwarz_norms(&B, Qn);
+    fxo_pnorm(S, l, P, Pn);
+    memset(K, 0, sizeof(double) * (size_t)n * n);
+    double nint = 0, nq = 0, nprimq = 0;
+    double buf[ONC * ONC * ONC * ONC];
+    for (int a = 0; a < S; ++a)
+        for (int b = 0; b <= a; ++b)
+            for (int c = 0; c <= a; ++c)
+                for (int d = 0; d <= c; ++d) {
+                    if (c * (c + 1) / 2 + d > a * (a + 1) / 2 + b) continue;
+                    const int sh[4] = {a, b, c, d};
+                    /* the distinct images (p,q,r,s), the slot map of each (pidx) and
+                       whether its own bound keeps it */
+                    int img[8][4], pidx[8], keep[8], nimg = 0, any = 0;
+                    for (int x = 0; x < 8; ++x) {
+                        int t[4];
+                        for (int y = 0; y < 4; ++y) t[y] = sh[perm[x][y]];
+                        int dup = 0;
+                        for (int z = 0; z < nimg && !dup; ++z)
+                            dup = img[z][0] == t[0] && img[z][1] == t[1] && img[z][2] == t[2] && img[z][3] == t[3];
+                        if (dup) continue;
+                        memcpy(img[nimg], t, sizeof(t));
+                        const double beta = (Qn[(size_t)t[0] * S + t[1]] * Qn[(size_t)t[2] * S + t[3]]) *
+                                            Pn[(size_t)t[1] * S + t[2]];
+                        pidx[nimg] = x;
+                        keep[nimg] = tau < 0.0 || beta > tau;
+                        any |= keep[nimg];
+                        ++nimg;
+                    }
+                    if (!any) continue;
+                    const oshell* Sh[4] = {&B.sh[a], &B.sh[b], &B.sh[c], &B.sh[d]};
+                    eri_quartet(Sh[0], Sh[1], Sh[2], Sh[3], 0, buf);
+                    nint += 1;
+                    nprimq += (double)Sh[0]->nprim * Sh[1]->nprim * Sh[2]->nprim * Sh[3]->nprim;
+                    const int nc4[4] = {ncart(Sh[0]->l), ncart(Sh[1]->l), ncart(Sh[2]->l), ncart(Sh[3]->l)};
+                    for (int z = 0; z < nimg; ++z) {
+                        if (!keep[z]) continue;
+                        const int* pm = perm[pidx[z]];
+                        const oshell *Ps = Sh[pm[0]], *Qs = Sh[pm[1]], *Rs = Sh[pm[2]], *Ss = Sh[pm[3]];
+                        const int np_ = nc4[pm[0]], nq_ = nc4[pm[1]], nr_ = nc4[pm[2]], ns_ = nc4[pm[3]];
+                        for (int i = 0; i < np_; ++i)
+                            for (int m = 0; m < ns_; ++m) {
+                                double acc = 0.0;
+                                for (int j = 0; j < nq_; ++j)
+                                    for (int k = 0; k < nr_; ++k) {
+                                        int t[4];
+                                        t[pm[0]] = i; t[pm[1]] = j; t[pm[2]] = k; t[pm[3]] = m;
+                                        const double I = buf[((t[0] * nc4[1] + t[1]) * nc4[2] + t[2]) * nc4[3] + t[3]];
+                                        acc += I * P[(size_t)(Qs->f0 + j) * n + (Rs->f0 + k)];
+                                    }
+                                K[(size_t)(Ps->f0 + i) * n + (Ss->f0 + m)] += acc;
+                            }
+                        nq += 1;
+                    }
+                }
+    if (stats) { stats[0] = nint; stats[1] = nq; stats[2] = nprimq; }
+    free(Qn); free(Pn); free(B.sh);
+    return 0;
+}
+
+/*
  * Overlap integrals (phi_mu|phi_nu) of the normalised contracted functions,
  * by the Hermite expansion: a Gaussian product in one direction is
  * sum_t E_t^{ij} Lambda_t, and only the t = 0 Hermite function has a
