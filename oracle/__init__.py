@@ -163,15 +163,18 @@ def exchange_sym8(s, P=None, tau=None):
     """K through the permutational symmetry of Section IV: each unique shell
     quartet evaluated once and contracted into every ordered quartet it
     stands for that its own bound keeps.  stats: unique quartets evaluated,
-    ordered quartets contracted, primitive quartets evaluated."""
+    ordered quartets contracted, primitive quartets evaluated, and the
+    evaluated quartets by symmetry block: full (eight distinct images, all
+    kept), diagonal (coinciding indices, all kept), sparse (an image culled)."""
     P = s.P if P is None else P
     tau = s.tau if tau is None else tau
     n = s.nbf
     K = np.zeros(n * n)
-    st = np.zeros(3)
+    st = np.zeros(6)
     _check(lib().fxo_exchange_sym8(*_sh(s), np.ascontiguousarray(P, np.float64), float(tau), K, st),
            "exchange_sym8")
-    return K.reshape(n, n), {"integrals": int(st[0]), "quartets": int(st[1]), "prim_quartets": int(st[2])}
+    return K.reshape(n, n), {"integrals": int(st[0]), "quartets": int(st[1]), "prim_quartets": int(st[2]),
+                             "full": int(st[3]), "diagonal": int(st[4]), "sparse": int(st[5])}
 
 
 def exchange_blocks(s, pairs, P=None, tau=None, Qn=None, Pn=None):

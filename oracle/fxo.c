@@ -540,7 +540,12 @@ int fxo_exchange(int nshell, const int32_t* l, const int32_t* nprim, const doubl
  * Serial: the contributions of one integral land in up to eight K blocks.
  * stats (nullable): [0] unique quartets whose integrals were evaluated,
  * [1] ordered quartets contracted (fxo_exchange's computed count), [2]
- * primitive quartets of the evaluated integrals.
+ * primitive quartets of the evaluated integrals, and a shell-level analogue
+ * of the paper's breakdown by symmetry block (its Fig. 2): of the evaluated
+ * quartets, [3] those with eight distinct images all kept (the full 4-fold
+ * contraction of Eq. 9 on both pairs), [4] those with coinciding indices
+ * (fewer distinct images, all kept: the diagonal cases), [5] those with
+ * some distinct image culled by its own bound (the "sparse" cases).
  */
 int fxo_exchange_sym8(int nshell, const int32_t* l, const int32_t* nprim, const double* center,
                       const double* exps, const double* coefs, const double* P, double tau, double* K,
@@ -555,7 +560,7 @@ int fxo_exchange_sym8(int nshell, const int32_t* l, const int32_t* nprim, const 
     schwarz_norms(&B, Qn);
     fxo_pnorm(S, l, P, Pn);
     memset(K, 0, sizeof(double) * (size_t)n * n);
-    double nint = 0, nq = 0, nprimq = 0;
+    double nint = 0, nq = 0, nprimq = 0, nfull = 0, ndiag = 0, nsparse = 0;
     double buf[ONC * ONC * ONC * ONC];
     for (int a = 0; a < S; ++a)
         for (int b = 0; b <= a; ++b)
@@ -582,6 +587,11 @@ int fxo_exchange_sym8(int nshell, const int32_t* l, const int32_t* nprim, const 
                         ++nimg;
                     }
                     if (!any) continue;
+                    int nkeep = 0;
+                    for (int z = 0; z < nimg; ++z) nkeep += keep[z];
+                    if (nkeep < nimg) nsparse += 1;
+                    else if (nimg == 8) nfull += 1;
+                    else ndiag += 1;
                     const oshell* Sh[4] = {&B.sh[a], &B.sh[b], &B.sh[c], &B.sh[d]};
                     eri_quartet(Sh[0], Sh[1], Sh[2], Sh[3], 0, buf);
                     nint += 1;
@@ -607,7 +617,10 @@ int fxo_exchange_sym8(int nshell, const int32_t* l, const int32_t* nprim, const 
                         nq += 1;
                     }
                 }
-    if (stats) { stats[0] = nint; stats[1] = nq; stats[2] = nprimq; }
+    if (stats) {
+        stats[0] = nint; stats[1] = nq; stats[2] = nprimq;
+        stats[3] = nfull; stats[4] = ndiag; stats[5] = nsparse;
+    }
     free(Qn); free(Pn); free(B.sh);
     return 0;
 }

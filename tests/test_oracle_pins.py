@@ -632,6 +632,10 @@ def test_symmetric_reuse_gives_the_same_K(cube10, tau):
         assert sts["integrals"] == M * (M + 1) // 2     # every canonical quartet
         assert sts["quartets"] == S ** 4
         assert sts["integrals"] * 7 < sts["quartets"]
+        # nothing culled; eight distinct images iff a != b, c != d and ab != cd
+        Pp = S * (S - 1) // 2
+        assert sts["sparse"] == 0 and sts["full"] == Pp * (Pp - 1) // 2
+    assert sts["full"] + sts["diagonal"] + sts["sparse"] == sts["integrals"]
 
 
 def test_symmetric_reuse_with_a_nonsymmetric_density(cube10):
