@@ -118,8 +118,9 @@ def test_learned_model_predicts_unit_time_better_than_bound_only(recorded):
 
 
 @pytest.mark.xfail(strict=False, reason="the learned unit order does not yet beat the bound-only order: "
-                   "4000-atom s+p slab, 5 alternating runs each, 20.52 s learned vs 20.31 s bound-only "
-                   "(K bitwise equal); with one unit per workgroup the order inside a launch has little leverage")
+                   "4000-atom s+p slab, 5 alternating runs each, 20.52 s learned vs 20.31 s bound-only; "
+                   "1000-atom s+p+d cluster, 14.74 s vs 14.68 s (K bitwise equal); with one unit per "
+                   "workgroup the order inside a launch has little leverage")
 def test_learned_order_builds_no_slower_than_bound_only():
     """The shipped model's unit order against the bound-only order on a
     250-atom s+p+d cluster, 5 alternating runs each: same K bitwise, and the
